@@ -1,0 +1,220 @@
+/*
+ * flinng.h -- C ABI of the MI355X (gfx950) FLINNG library.
+ *
+ * FLINNG (Filters to Identify Near-Neighbor Groups; Engels, Coleman and
+ * Shrivastava, "Practical Near Neighbor Search via Group Testing", 2021)
+ * answers randomized nearest-neighbour queries (Definition 1) with a B x R
+ * grid of group tests.  Each repetition r spreads the N points evenly over B
+ * groups by a random permutation (Algorithm 1).  Each group's test is a
+ * distance-sensitive Bloom filter (Section 3, Theorem 1) built from L shared
+ * LSH functions, each the concatenation of K hashes (Section 3, concatenation
+ * trick).  The filters are stored as one reverse index per LSH function:
+ * bucket value -> list of cells (Section 5, Implementation).  A query counts,
+ * for every cell, in how many tables it collides, then decodes by threshold
+ * relaxation (Algorithm 3, equivalent to Algorithm 2 at decreasing
+ * thresholds) and returns k point ids.
+ *
+ * Notation in this header: L = number of LSH tables (the paper's m),
+ * K = hashes concatenated per table (the paper's L), R repetitions, B groups
+ * per repetition, cell id c = r*B + b.
+ *
+ * Conventions for every entry point:
+ *  - Returns FLINNG_OK (0) or a negative error code; on error a message is
+ *    available from flinng_last_error() (thread-local) and no output is
+ *    guaranteed.  No C++ exception crosses this boundary.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All device work is
+ *    enqueued on it.  Entry points that return host results synchronize the
+ *    stream before returning; entry points whose outputs are device pointers
+ *    return as soon as the work is enqueued.
+ *  - Pointers flagged "device" must be device (or managed) memory of the
+ *    current HIP device; "host" pointers are ordinary host memory.
+ *  - The library never keeps a pointer to caller memory after the call's
+ *    stream work has completed.
+ */
+#ifndef FLINNG_H
+#define FLINNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (negative errno values) ------------------------------ */
+#define FLINNG_OK 0
+#define FLINNG_EINVAL (-22)    /* invalid argument or parameter            */
+#define FLINNG_ENOMEM (-12)    /* device or host allocation failed          */
+#define FLINNG_EDEVICE (-5)    /* HIP runtime / kernel launch error         */
+#define FLINNG_EBUSY (-16)     /* serving: admission refused                */
+#define FLINNG_ETIMEDOUT (-110)/* serving: wait timed out                   */
+#define FLINNG_ESTATE (-77)    /* serving: server shut down / bad ticket    */
+
+/* ---- hash families ----------------------------------------------------- */
+/* Dense rows hashed by signed random projections: bit j of table t is 1 iff
+ * the exact dot product of the row with hyperplane t*K+j is > 0; the bucket
+ * of table t is sum_j bit_j 2^j (K bits).  Item sets hashed by MinHash: K
+ * 32-bit minima per table folded to `bucket_bits` bits. */
+enum flinng_family {
+    FLINNG_SRP_F32 = 0,     /* dense, values fp32, row-major count x dim     */
+    FLINNG_SRP_BF16 = 1,    /* dense, values bf16 bit patterns (uint16_t)    */
+    FLINNG_MINHASH_U32 = 2, /* sets of uint32_t items, CSR offsets           */
+    FLINNG_MINHASH_U64 = 3  /* sets of uint64_t items, CSR offsets           */
+};
+
+/* Index parameters (Appendix "Hyperparameters": R, B, m, L of the paper). */
+typedef struct flinng_params {
+    uint32_t family;      /* enum flinng_family                               */
+    uint32_t dim;         /* dense: row length d >= 1; sets: ignored           */
+    uint32_t K;           /* hashes per table: SRP bits 1..24, MinHash 1..32  */
+    uint32_t L;           /* tables (the paper's m): 1..255                   */
+    uint32_t R;           /* repetitions: 1..16                               */
+    uint32_t B;           /* groups per repetition: 1..65536, B <= N          */
+    uint32_t bucket_bits; /* sets: bucket width 1..24; dense: must be 0 or K  */
+    uint32_t reserved;    /* must be 0                                        */
+    uint64_t seed;        /* seeds the hyperplanes, MinHash keys and groups   */
+} flinng_params;
+
+/* A batch of points or queries. */
+typedef struct flinng_input {
+    const void *values;       /* dense: count*dim elements, row-major;
+                                 sets: concatenated items                     */
+    const uint64_t *offsets;  /* sets: count+1 nondecreasing offsets into
+                                 values (offsets[0] = 0); dense: NULL         */
+    uint64_t count;           /* number of rows / sets                        */
+    uint32_t on_device;       /* 1: values/offsets are device pointers        */
+    uint32_t reserved;        /* must be 0                                    */
+} flinng_input;
+
+typedef struct flinng_index flinng_index;
+
+/* Facts about a built index (sizes in elements unless noted). */
+typedef struct flinng_index_info {
+    uint64_t N;               /* indexed points                               */
+    uint64_t list_entries;    /* total reverse-index list entries             */
+    uint64_t device_bytes;    /* device memory held by the index              */
+    uint32_t family, dim, K, L, R, B, bucket_bits;
+    uint32_t cell_id_bytes;   /* 2 when R*B <= 65536, else 4                  */
+    uint64_t srp_rechecked;   /* build: projections recomputed in FP64        */
+    uint64_t srp_exact;       /* build: of those, decided by the exact sum    */
+} flinng_index_info;
+
+/*
+ * flinng_build -- one-pass index construction (Algorithm 1 plus the reverse
+ * index of Section 5).
+ *  p      (host)  parameters; validated (FLINNG_EINVAL on any violation,
+ *                 including B > N, dense dim mismatch, L*K*dim overflow).
+ *  data   (host struct) the N points; values/offsets on host or device per
+ *                 data->on_device.  Borrowed for the duration of the call;
+ *                 the library does not store the data (no vectors are kept).
+ *  out    (host)  receives the new index; the library owns all its device
+ *                 memory until flinng_index_free.
+ * The call synchronizes `stream` before returning.
+ */
+int flinng_build(const flinng_params *p, const flinng_input *data,
+                 void *stream, flinng_index **out);
+
+/*
+ * flinng_query -- batched query: hash, count per cell through the reverse
+ * index (Section 5), decode by threshold relaxation (Algorithm 3).
+ *  q        (host struct) nq = q->count queries of the index's family.
+ *  k        neighbours per query, 1..4096.
+ *  ids      (host or device per out_on_device) nq*k uint32, row-major:
+ *           point ids in the order Algorithm 3 reports them (cells by
+ *           descending count, ties by ascending cell id; points within a cell
+ *           by ascending id).  Padded with 0xFFFFFFFF when k > N.
+ *  scores   same layout: the count of the cell that completed each point,
+ *           i.e. the relaxed threshold at which it is reported; 0 for pads.
+ *           May be NULL.
+ *  persistent  0: one workgroup per query; 1: a persistent grid that pulls
+ *           queries from a device counter (for uneven batches in one launch).
+ * Device outputs: the call returns once the work is enqueued on `stream`.
+ * Host outputs: the call synchronizes `stream`.  The index is read-only, so
+ * concurrent calls on different streams are allowed.
+ */
+int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
+                 uint32_t *ids, uint32_t *scores, uint32_t out_on_device,
+                 uint32_t persistent, void *stream);
+
+/* Release an index and all its device memory (NULL is allowed). */
+void flinng_index_free(flinng_index *idx);
+
+/* Index facts (host struct). */
+int flinng_index_get_info(const flinng_index *idx, flinng_index_info *info);
+
+/* Last error message of the calling thread ("" if none). */
+const char *flinng_last_error(void);
+
+/* ---- layered parity hooks ---------------------------------------------- */
+/* Bucket codes of a batch: codes[count*L] (host or device), row-major. */
+int flinng_debug_hash(const flinng_index *idx, const flinng_input *q,
+                      uint32_t *codes, uint32_t out_on_device, void *stream);
+
+/* Per-cell collision counts of a batch: counts[count*R*B] uint8 (host or
+ * device), cell id c = r*B + b. */
+int flinng_debug_counts(const flinng_index *idx, const flinng_input *q,
+                        uint8_t *counts, uint32_t out_on_device, void *stream);
+
+/*
+ * Export the index to host arrays (tests; small indexes).
+ *  offsets  L*(2^bits + 1) uint64: absolute positions into cells of each
+ *           table's bucket lists (bits = K for dense, bucket_bits for sets).
+ *  cells    list_entries uint32 cell ids, each bucket's list ascending.
+ *  groups   R*N uint32, repetition-major: group of point x in repetition r.
+ * Any pointer may be NULL to skip it.  Synchronizes `stream`.
+ */
+int flinng_index_export(const flinng_index *idx, uint64_t *offsets,
+                        uint32_t *cells, uint32_t *groups, void *stream);
+
+/* ---- serving: continuous batching over resident indexes ----------------- */
+typedef struct flinng_server flinng_server;
+
+typedef struct flinng_serve_config {
+    uint64_t mem_budget;      /* device bytes the server may hold for
+                                 in-flight batches (inputs, outputs, scratch) */
+    uint32_t max_inflight;    /* batches on the GPU at once (streams), 1..16  */
+    uint32_t max_batch;       /* queries per launched batch, >= 1             */
+    uint32_t max_queue;       /* queued requests before submit refuses        */
+    uint32_t persistent;      /* launch batches with the persistent grid      */
+    uint64_t linger_ns;       /* wait this long for more requests when a
+                                 slot is free but the batch is not full       */
+} flinng_serve_config;
+
+typedef struct flinng_serve_stats {
+    uint64_t submitted, completed, rejected, batches, queries;
+    double wall_s;            /* since create                                 */
+    double qps;               /* completed queries / wall_s                   */
+    double p50_ms, p99_ms, max_ms; /* completion - submit latency per request */
+    double mean_batch;        /* queries per launched batch                   */
+    uint64_t peak_mem_bytes;  /* peak admitted in-flight memory               */
+} flinng_serve_stats;
+
+/* Create a server over n_idx resident indexes (borrowed; they must outlive
+ * the server).  One scheduler thread, cfg->max_inflight HIP streams. */
+int flinng_serve_create(flinng_index *const *indexes, uint32_t n_idx,
+                        const flinng_serve_config *cfg, flinng_server **out);
+
+/* Submit one request (a batch of queries for index slot idx_slot, host
+ * input, copied before return).  *ticket identifies it.  FLINNG_EBUSY when
+ * the queue is full or the request alone exceeds the memory budget. */
+int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot,
+                        const flinng_input *q, uint32_t k, uint64_t *ticket);
+
+/* Wait for a request; copies its results (count*k each, host) and releases
+ * the ticket.  timeout_ns < 0 waits forever.  FLINNG_ETIMEDOUT leaves the
+ * ticket valid. */
+int flinng_serve_wait(flinng_server *srv, uint64_t ticket, uint32_t *ids,
+                      uint32_t *scores, int64_t timeout_ns);
+
+/* 1 if done, 0 if not yet, negative on error. */
+int flinng_serve_poll(flinng_server *srv, uint64_t ticket);
+
+int flinng_serve_stats_get(flinng_server *srv, flinng_serve_stats *st);
+
+/* Drain in-flight work, then stop the scheduler and free the server.
+ * Requests not yet waited on are discarded. */
+void flinng_serve_destroy(flinng_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLINNG_H */

@@ -1,0 +1,164 @@
+"""FLINNG (group-testing near-neighbour search) on AMD MI355X / gfx950.
+
+Python face of the C ABI in include/flinng.h: build an index on the GPU,
+query it in batches, and serve mixed query streams with continuous batching.
+All computation runs in the HIP library (libflinng.so); this package only
+marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+
+from ._lib import (  # noqa: F401
+    SRP_F32, SRP_BF16, MINHASH_U32, MINHASH_U64, FlinngError, Params, Input,
+    IndexInfo, ServeConfig, ServeStats, check, lib, make_input, current_stream,
+    EBUSY, EINVAL, ENOMEM, ETIMEDOUT, ESTATE,
+)
+
+
+def _stream(stream):
+    if stream is None:
+        return current_stream()
+    if isinstance(stream, ctypes.c_void_p):
+        return stream
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+class Index:
+    """A FLINNG index resident on the current HIP device (flinng_build)."""
+
+    def __init__(self, data, family, K, L, R, B, seed, dim=None, bucket_bits=0,
+                 stream=None):
+        self.family = family
+        p = Params(family=family, K=K, L=L, R=R, B=B, bucket_bits=bucket_bits,
+                   reserved=0, seed=seed)
+        if family in (SRP_F32, SRP_BF16):
+            p.dim = dim if dim is not None else data.shape[1]
+        inp, keep = make_input(data, family)
+        h = ctypes.c_void_p()
+        check(lib().flinng_build(ctypes.byref(p), ctypes.byref(inp), _stream(stream),
+                                 ctypes.byref(h)))
+        self._h = h
+        del keep
+        self.info = self.get_info()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_info(self):
+        info = IndexInfo()
+        check(lib().flinng_index_get_info(self._h, ctypes.byref(info)))
+        return info
+
+    def query(self, q, k, persistent=False, stream=None, out=None):
+        """flinng_query.  Host inputs/outputs: returns numpy (ids, scores).
+        Device: pass out=(ids_tensor, scores_tensor or None) (uint32 as
+        torch.int32 storage) and the call only enqueues work."""
+        inp, keep = make_input(q, self.family)
+        nq = inp.count
+        if out is not None:
+            ids_t, sc_t = out
+            check(lib().flinng_query(self._h, ctypes.byref(inp), k, ids_t.data_ptr(),
+                                     sc_t.data_ptr() if sc_t is not None else None,
+                                     1, int(persistent), _stream(stream)))
+            return out
+        ids = np.empty((nq, k), dtype=np.uint32)
+        sc = np.empty((nq, k), dtype=np.uint32)
+        check(lib().flinng_query(self._h, ctypes.byref(inp), k, ids.ctypes.data,
+                                 sc.ctypes.data, 0, int(persistent), _stream(stream)))
+        del keep
+        return ids, sc
+
+    def debug_hash(self, q, stream=None):
+        inp, keep = make_input(q, self.family)
+        codes = np.empty((inp.count, self.info.L), dtype=np.uint32)
+        check(lib().flinng_debug_hash(self._h, ctypes.byref(inp), codes.ctypes.data, 0,
+                                      _stream(stream)))
+        return codes
+
+    def debug_counts(self, q, stream=None):
+        inp, keep = make_input(q, self.family)
+        c = np.empty((inp.count, self.info.R * self.info.B), dtype=np.uint8)
+        check(lib().flinng_debug_counts(self._h, ctypes.byref(inp), c.ctypes.data, 0,
+                                        _stream(stream)))
+        return c
+
+    def export(self, stream=None):
+        """(offsets [L, 2^bits+1] uint64, cells uint32, groups [R, N] uint32)."""
+        i = self.info
+        offs = np.empty((i.L, (1 << i.bucket_bits) + 1), dtype=np.uint64)
+        cells = np.empty(max(i.list_entries, 1), dtype=np.uint32)
+        groups = np.empty((i.R, i.N), dtype=np.uint32)
+        check(lib().flinng_index_export(self._h, offs.ctypes.data, cells.ctypes.data,
+                                        groups.ctypes.data, _stream(stream)))
+        return offs, cells[:i.list_entries], groups
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().flinng_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over resident indexes (flinng_serve_*)."""
+
+    def __init__(self, indexes, mem_budget=1 << 30, max_inflight=4, max_batch=4096,
+                 max_queue=1 << 20, persistent=False, linger_ns=0):
+        self._indexes = list(indexes)
+        arr = (ctypes.c_void_p * len(self._indexes))(*[ix.handle.value for ix in self._indexes])
+        cfg = ServeConfig(mem_budget=mem_budget, max_inflight=max_inflight,
+                          max_batch=max_batch, max_queue=max_queue,
+                          persistent=int(persistent), linger_ns=linger_ns)
+        h = ctypes.c_void_p()
+        check(lib().flinng_serve_create(arr, len(self._indexes), ctypes.byref(cfg),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, slot, q, k):
+        inp, keep = make_input(q, self._indexes[slot].family)
+        t = ctypes.c_uint64()
+        check(lib().flinng_serve_submit(self._h, slot, ctypes.byref(inp), k, ctypes.byref(t)))
+        return t.value, int(inp.count)
+
+    def try_submit(self, slot, q, k):
+        """Like submit, but returns (None, rc) instead of raising on refusal."""
+        inp, keep = make_input(q, self._indexes[slot].family)
+        t = ctypes.c_uint64()
+        rc = lib().flinng_serve_submit(self._h, slot, ctypes.byref(inp), k, ctypes.byref(t))
+        return (t.value if rc == 0 else None), rc
+
+    def wait(self, ticket, nq, k, timeout_ns=-1):
+        ids = np.empty((nq, k), dtype=np.uint32)
+        sc = np.empty((nq, k), dtype=np.uint32)
+        check(lib().flinng_serve_wait(self._h, ticket, ids.ctypes.data, sc.ctypes.data,
+                                      timeout_ns))
+        return ids, sc
+
+    def poll(self, ticket):
+        rc = lib().flinng_serve_poll(self._h, ticket)
+        if rc < 0:
+            check(rc)
+        return rc == 1
+
+    def stats(self):
+        st = ServeStats()
+        check(lib().flinng_serve_stats_get(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().flinng_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,331 @@
+// Exported C ABI: argument validation, orchestration of the build and query
+// pipelines, and error mapping (no C++ exception crosses the boundary).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "flinng_internal.h"
+
+namespace flinng {
+
+static thread_local std::string g_err;
+
+void set_last_error(const std::string &msg) { g_err = msg; }
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+DevBuf::DevBuf(size_t bytes, hipStream_t s) : stream(s) {
+    if (bytes == 0) return;
+    hipError_t e = hipMallocAsync(&ptr, bytes, s);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? FLINNG_ENOMEM : FLINNG_EDEVICE,
+             "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                 hipGetErrorString(e));
+    }
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFreeAsync(ptr, stream);
+    ptr = nullptr;
+}
+
+DevBuf::~DevBuf() { release(); }
+
+template <class F>
+static int guard(F &&f) {
+    try {
+        f();
+        set_last_error("");
+        return FLINNG_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return FLINNG_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(std::string("internal error: ") + e.what());
+        return FLINNG_EDEVICE;
+    } catch (...) {
+        set_last_error("internal error");
+        return FLINNG_EDEVICE;
+    }
+}
+
+static void require(bool ok, const std::string &msg) {
+    if (!ok) fail(FLINNG_EINVAL, msg);
+}
+
+static void validate_params(const flinng_params &p, uint64_t N) {
+    require(p.family <= FLINNG_MINHASH_U64, "unknown family");
+    require(p.reserved == 0, "reserved must be 0");
+    require(p.L >= 1 && p.L <= 255, "L (tables) must be in 1..255");
+    require(p.R >= 1 && p.R <= 16, "R (repetitions) must be in 1..16");
+    require(p.B >= 1 && p.B <= 65536, "B (groups) must be in 1..65536");
+    require(N >= 1, "empty dataset");
+    require(N <= 0xFFFFFFFEull, "at most 2^32-2 points");
+    require(p.B <= N, "B must not exceed N");
+    if (is_dense(p.family)) {
+        require(p.dim >= 1 && p.dim <= (1u << 20), "dim must be in 1..2^20");
+        require(p.K >= 1 && p.K <= 24, "SRP K (bits per table) must be in 1..24");
+        require(p.bucket_bits == 0 || p.bucket_bits == p.K, "SRP bucket_bits must be 0 or K");
+    } else {
+        require(p.K >= 1 && p.K <= 32, "MinHash K must be in 1..32");
+        require(p.bucket_bits >= 1 && p.bucket_bits <= 24, "MinHash bucket_bits must be in 1..24");
+    }
+}
+
+static void validate_input(const flinng_input *in, uint32_t family, const char *what) {
+    require(in != nullptr, std::string(what) + " is NULL");
+    require(in->reserved == 0, std::string(what) + ".reserved must be 0");
+    if (in->count == 0) return;
+    require(in->values != nullptr || !is_dense(family), std::string(what) + ".values is NULL");
+    if (!is_dense(family)) require(in->offsets != nullptr, std::string(what) + ".offsets is NULL");
+}
+
+static flinng_input slice(const flinng_input &in, const Index &ix, uint64_t begin, uint64_t n) {
+    flinng_input s = in;
+    s.count = n;
+    if (is_dense(ix.p.family)) {
+        const size_t esz = ix.p.family == FLINNG_SRP_F32 ? 4 : 2;
+        s.values = static_cast<const char *>(in.values) + begin * ix.p.dim * esz;
+    } else {
+        s.offsets = in.offsets + begin;
+    }
+    return s;
+}
+
+static void free_index(Index *ix) {
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    if (ix->offsets) (void)hipFree(ix->offsets);
+    if (ix->cells) (void)hipFree(ix->cells);
+    if (ix->grp) (void)hipFree(ix->grp);
+    if (ix->mem) (void)hipFree(ix->mem);
+    if (ix->hyp) (void)hipFree(ix->hyp);
+    if (ix->hypnorm) (void)hipFree(ix->hypnorm);
+    delete ix;
+}
+
+template <class T>
+static T *dmalloc(uint64_t n, uint64_t &acc) {
+    void *p = nullptr;
+    const size_t bytes = std::max<uint64_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? FLINNG_ENOMEM : FLINNG_EDEVICE,
+             "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    acc += bytes;
+    return static_cast<T *>(p);
+}
+
+}  // namespace flinng
+
+using namespace flinng;
+
+extern "C" {
+
+const char *flinng_last_error(void) { return g_err.c_str(); }
+
+int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
+                 flinng_index **out) {
+    return guard([&] {
+        require(p && data && out, "NULL argument");
+        *out = nullptr;
+        validate_input(data, p->family, "data");
+        validate_params(*p, data->count);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Index *ix = new Index();
+        try {
+            ix->p = *p;
+            ix->N = data->count;
+            FL_HIP(hipGetDevice(&ix->device));
+            const bool dense = is_dense(p->family);
+            ix->nbits = dense ? p->K : p->bucket_bits;
+            if (dense) ix->p.bucket_bits = p->K;
+            ix->dpad = dense ? ((p->dim + 31) / 32) * 32 : 0;
+            ix->Rp = 1;
+            while (ix->Rp < p->R) ix->Rp <<= 1;
+            const uint32_t Bp = (p->B + 3) & ~3u;
+            ix->cell_bytes = ((uint64_t)p->R * Bp <= 65536) ? 2 : 4;
+            const uint64_t N = ix->N, nbk = nbuckets(*ix);
+            uint64_t bytes = 0;
+            ix->offsets = dmalloc<uint32_t>((uint64_t)p->L * (nbk + 1), bytes);
+            ix->grp = dmalloc<uint16_t>(N * ix->Rp, bytes);
+            ix->mem = dmalloc<uint32_t>(N * p->R, bytes);
+            if (dense) {
+                ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
+                ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);
+                srp_make_hyperplanes(*ix, s);
+            }
+            // hash all points (in chunks to bound scratch memory)
+            DevBuf codes(N * p->L * 4, s);
+            const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix->dpad * 16))
+                                         : (1ull << 20);
+            for (uint64_t b0 = 0; b0 < N; b0 += chunk) {
+                const uint64_t n = std::min(chunk, N - b0);
+                flinng_input part = slice(*data, *ix, b0, n);
+                uint64_t ctr[2] = {0, 0};
+                hash_batch(*ix, part, codes.as<uint32_t>() + b0 * p->L, s, dense ? ctr : nullptr);
+                ix->srp_rechecked += ctr[0];
+                ix->srp_exact += ctr[1];
+            }
+            build_groups(*ix, s);
+            build_lists(*ix, codes.as<uint32_t>(), s);
+            FL_HIP(hipStreamSynchronize(s));
+            bytes += ix->list_entries * ix->cell_bytes;
+            ix->device_bytes = bytes;
+        } catch (...) {
+            free_index(ix);
+            throw;
+        }
+        *out = reinterpret_cast<flinng_index *>(ix);
+    });
+}
+
+void flinng_index_free(flinng_index *idx) { free_index(reinterpret_cast<Index *>(idx)); }
+
+int flinng_index_get_info(const flinng_index *idx, flinng_index_info *info) {
+    return guard([&] {
+        require(idx && info, "NULL argument");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        std::memset(info, 0, sizeof(*info));
+        info->N = ix.N;
+        info->list_entries = ix.list_entries;
+        info->device_bytes = ix.device_bytes;
+        info->family = ix.p.family;
+        info->dim = ix.p.dim;
+        info->K = ix.p.K;
+        info->L = ix.p.L;
+        info->R = ix.p.R;
+        info->B = ix.p.B;
+        info->bucket_bits = ix.nbits;
+        info->cell_id_bytes = ix.cell_bytes;
+        info->srp_rechecked = ix.srp_rechecked;
+        info->srp_exact = ix.srp_exact;
+    });
+}
+
+int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uint32_t *ids,
+                 uint32_t *scores, uint32_t out_on_device, uint32_t persistent, void *stream) {
+    return guard([&] {
+        require(idx != nullptr, "index is NULL");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        validate_input(q, ix.p.family, "queries");
+        require(ids != nullptr, "ids is NULL");
+        require(k >= 1 && k <= query_max_k(), "k must be in 1..4096");
+        const uint64_t nq = q->count;
+        if (nq == 0) return;
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf codes(nq * ix.p.L * 4, s);
+        hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        DevBuf work(persistent ? 4 : 0, s);
+        if (out_on_device) {
+            query_launch(ix, codes.as<uint32_t>(), nq, k, ids, scores, persistent != 0, s,
+                         work.as<uint32_t>());
+        } else {
+            DevBuf dids(nq * k * 4, s), dsc(scores ? nq * k * 4 : 0, s);
+            query_launch(ix, codes.as<uint32_t>(), nq, k, dids.as<uint32_t>(),
+                         scores ? dsc.as<uint32_t>() : nullptr, persistent != 0, s,
+                         work.as<uint32_t>());
+            FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
+            if (scores) FL_HIP(hipMemcpyAsync(scores, dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+int flinng_debug_hash(const flinng_index *idx, const flinng_input *q, uint32_t *codes,
+                      uint32_t out_on_device, void *stream) {
+    return guard([&] {
+        require(idx && codes, "NULL argument");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        validate_input(q, ix.p.family, "queries");
+        const uint64_t nq = q->count;
+        if (nq == 0) return;
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (out_on_device) {
+            hash_batch(ix, *q, codes, s, nullptr);
+        } else {
+            DevBuf d(nq * ix.p.L * 4, s);
+            hash_batch(ix, *q, d.as<uint32_t>(), s, nullptr);
+            FL_HIP(hipMemcpyAsync(codes, d.ptr, nq * ix.p.L * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+int flinng_debug_counts(const flinng_index *idx, const flinng_input *q, uint8_t *counts,
+                        uint32_t out_on_device, void *stream) {
+    return guard([&] {
+        require(idx && counts, "NULL argument");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        validate_input(q, ix.p.family, "queries");
+        const uint64_t nq = q->count;
+        if (nq == 0) return;
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const uint64_t nc = (uint64_t)ix.p.R * ix.p.B;
+        DevBuf codes(nq * ix.p.L * 4, s);
+        hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        if (out_on_device) {
+            counts_launch(ix, codes.as<uint32_t>(), nq, counts, s);
+        } else {
+            DevBuf d(nq * nc, s);
+            counts_launch(ix, codes.as<uint32_t>(), nq, d.as<uint8_t>(), s);
+            FL_HIP(hipMemcpyAsync(counts, d.ptr, nq * nc, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+int flinng_index_export(const flinng_index *idx, uint64_t *offsets, uint32_t *cells,
+                        uint32_t *groups, void *stream) {
+    return guard([&] {
+        require(idx != nullptr, "index is NULL");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const uint64_t nbk = nbuckets(ix);
+        const uint32_t B = ix.p.B, Bp = (B + 3) & ~3u;
+        if (offsets) {
+            std::vector<uint32_t> o((size_t)ix.p.L * (nbk + 1));
+            FL_HIP(hipMemcpyAsync(o.data(), ix.offsets, o.size() * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+            for (size_t i = 0; i < o.size(); ++i) offsets[i] = o[i];
+        }
+        if (cells) {
+            const uint64_t n = ix.list_entries;
+            if (ix.cell_bytes == 2) {
+                std::vector<uint16_t> c(n);
+                if (n) FL_HIP(hipMemcpyAsync(c.data(), ix.cells, n * 2, hipMemcpyDeviceToHost, s));
+                FL_HIP(hipStreamSynchronize(s));
+                for (uint64_t i = 0; i < n; ++i) cells[i] = (c[i] / Bp) * B + c[i] % Bp;
+            } else {
+                std::vector<uint32_t> c(n);
+                if (n) FL_HIP(hipMemcpyAsync(c.data(), ix.cells, n * 4, hipMemcpyDeviceToHost, s));
+                FL_HIP(hipStreamSynchronize(s));
+                for (uint64_t i = 0; i < n; ++i) cells[i] = (c[i] / Bp) * B + c[i] % Bp;
+            }
+        }
+        if (groups) {
+            std::vector<uint16_t> g(ix.N * ix.Rp);
+            FL_HIP(hipMemcpyAsync(g.data(), ix.grp, g.size() * 2, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+            for (uint32_t r = 0; r < ix.p.R; ++r)
+                for (uint64_t x = 0; x < ix.N; ++x) groups[(uint64_t)r * ix.N + x] = g[x * ix.Rp + r];
+        }
+    });
+}
+
+}  // extern "C"

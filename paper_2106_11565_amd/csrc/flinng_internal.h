@@ -1,0 +1,141 @@
+// Internal declarations of the gfx950 FLINNG library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/flinng.h"
+
+namespace flinng {
+
+// ---------------------------------------------------------------------------
+// Errors: every ABI function catches flinng::Error and maps it to a code and
+// the thread-local message.
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define FL_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            ::flinng::fail(e_ == hipErrorOutOfMemory ? FLINNG_ENOMEM          \
+                                                     : FLINNG_EDEVICE,        \
+                           std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FL_CHECK_LAUNCH() FL_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Counter-based generator shared by every random object of the method:
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014) applied to
+// state s + (i+1) * 0x9E3779B97F4A7C15, i.e. the i-th output of a SplitMix64
+// stream started at s.  Stream keys: sm64(seed, tag).
+enum : uint64_t { TAG_HYP = 1, TAG_MINHASH = 2, TAG_GROUP = 3 };
+
+__host__ __device__ inline uint64_t splitmix_finalize(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm64(uint64_t s, uint64_t i) {
+    return splitmix_finalize(s + (i + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+
+// ---------------------------------------------------------------------------
+// A built index.  Device layout (all arrays owned by the index):
+//   offsets   [L][nbuckets+1] uint32  absolute positions into `cells`
+//   cells     [list_entries]  uint16 (R*B <= 65536) or uint32 cell ids,
+//             each bucket's list ascending (a Bloom filter bit set once)
+//   grp       [N][Rp]         uint16 group of point x in repetition r
+//             (Rp = R rounded up to a power of two; point-major so one
+//             vector load gathers all R groups of a candidate)
+//   mem       [R][N]          uint32 members of cell (r,b) at
+//             [b*floor(N/B) + min(b, N mod B), +size), ascending id
+//   hyp       [L*K][dpad]     bf16 hyperplanes (dense families)
+//   hypnorm   [L*K]           fp32 Euclidean norms of the hyperplanes
+struct Index {
+    flinng_params p{};
+    uint64_t N = 0;
+    uint32_t nbits = 0;          // bucket width (K for SRP)
+    uint32_t dpad = 0;           // dense: dim rounded up to 32
+    uint32_t Rp = 1;
+    uint32_t cell_bytes = 2;
+    uint64_t list_entries = 0;
+    uint64_t device_bytes = 0;
+    uint64_t srp_rechecked = 0, srp_exact = 0;
+    int device = 0;
+    uint32_t *offsets = nullptr;
+    void *cells = nullptr;
+    uint16_t *grp = nullptr;
+    uint32_t *mem = nullptr;
+    uint16_t *hyp = nullptr;
+    float *hypnorm = nullptr;
+};
+
+inline uint64_t nbuckets(const Index &ix) { return 1ull << ix.nbits; }
+inline bool is_dense(uint32_t fam) { return fam == FLINNG_SRP_F32 || fam == FLINNG_SRP_BF16; }
+
+// Device scratch allocated on a stream (stream-ordered allocator).
+struct DevBuf {
+    void *ptr = nullptr;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t bytes, hipStream_t s);
+    ~DevBuf();
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), stream(o.stream) { o.ptr = nullptr; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            ptr = o.ptr;
+            stream = o.stream;
+            o.ptr = nullptr;
+        }
+        return *this;
+    }
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------------------
+// Hashing (hash_srp.hip, hash_minhash.hip).  All write codes[n][L] uint32.
+void srp_make_hyperplanes(Index &ix, hipStream_t s);
+// Returns (rechecked, exact) counts when counters != nullptr (synchronizes).
+void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
+              hipStream_t s, uint64_t *counters_host);
+void minhash_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
+                  hipStream_t s, double mean_hint = -1.0);
+// mean_hint: mean items per set of a device-resident set batch (<= 0: unknown)
+void hash_batch(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
+                hipStream_t s, uint64_t *counters_host, double mean_hint = -1.0);
+// Device bytes one batch of nq queries (nitems set items) needs in flight.
+uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k);
+
+// Sorting and scans (radix.hip).
+void device_exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n,
+                               hipStream_t s);
+// Stable LSD radix sort of 64-bit keys (bits [0, end_bit)) with optional
+// uint32 values; result in keys/vals (tmp buffers of the same size needed).
+void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals,
+                    uint32_t *vals_tmp, uint64_t n, int end_bit, hipStream_t s);
+
+// Build pieces (build.hip).
+void build_groups(Index &ix, hipStream_t s);
+void build_lists(Index &ix, const uint32_t *codes_dev, hipStream_t s);
+
+// Query (query.hip).
+void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
+                  uint32_t k, uint32_t *ids_dev, uint32_t *scores_dev,
+                  bool persistent, hipStream_t s, uint32_t *work_counter);
+void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
+                   uint8_t *counts_dev, hipStream_t s);
+size_t query_lds_bytes(const Index &ix, uint32_t k);
+uint32_t query_max_k();
+
+}  // namespace flinng

@@ -1,0 +1,554 @@
+// Batched FLINNG query on gfx950: count, threshold, decode.
+//
+// One workgroup owns one query at a time (a persistent grid pulls queries
+// from a device counter).  All per-query state lives in LDS:
+//   * the B*R cell counters as bytes (count <= L <= 255), 4 per dword,
+//     incremented with 32-bit LDS atomics while the workgroup walks the L
+//     reverse-index lists selected by the query's codes (Section 5: count how
+//     often each cell collides with the query);
+//   * per-repetition histograms of the nonzero counts;
+//   * a top-k key buffer.
+// Decode (Algorithm 3, threshold relaxation).  Walking cells by descending
+// count and reporting a point when all R of its cells have been walked means
+// a point x completes at its last-ranked cell, so the output is the k
+// smallest keys (255 - m(x), c*(x), x) with m(x) = min_r C[r, g_r(x)] and
+// c*(x) the largest cell id among x's cells of count m(x).  {x : m(x) >= t}
+// is Algorithm 2's answer at threshold t, and it lies inside the cells of
+// count >= t of any single repetition.  So a pass enumerates the members of
+// one repetition's cells with count >= t (t chosen from the histograms),
+// computes every candidate's key with one R-wide gather of its groups, and
+// keeps the smallest keys; the pass is final once at least k candidates have
+// m >= t.  When fewer than k points have m >= 1, the answer is completed
+// from repetition R-1: its positive cells hold every point whose last
+// zero-count cell lies in an earlier repetition, and the rest follow in
+// (cell, id) order from its zero-count cells.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "flinng_internal.h"
+
+namespace flinng {
+
+constexpr int QT = 256;          // threads per query workgroup
+constexpr int QW = QT / 64;      // wavefronts per workgroup
+constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
+
+struct QArgs {
+    const uint32_t *codes;
+    uint64_t nq;
+    const uint32_t *offsets;
+    const void *cells;
+    const uint16_t *grp;
+    const uint32_t *mem;
+    uint64_t N;
+    uint32_t L, R, Rp, B, Bp, nbits, k, cap;
+    uint32_t *ids;
+    uint32_t *scores;
+    uint8_t *counts_out;   // debug: write counters and skip decode
+    uint32_t *work;        // persistent: next query counter (nullptr: 1 WG/query)
+    uint32_t budget;
+};
+
+struct QLayout {
+    uint32_t cnt_words, hist_words, cap;
+    size_t off_cnt, off_hist, off_pre, off_start, off_buf, off_lb, off_lp, off_misc, total;
+};
+
+__host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp, uint32_t cap) {
+    QLayout l;
+    l.cnt_words = (R * Bp) / 4;
+    l.hist_words = QW * R * (L + 1);
+    l.cap = cap;
+    size_t o = 0;
+    l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned first
+    l.off_cnt = o;   o += (size_t)l.cnt_words * 4;
+    l.off_hist = o;  o += (size_t)l.hist_words * 4;
+    l.off_pre = o;   o += (size_t)(L + 1) * 4;
+    l.off_start = o; o += (size_t)L * 4;
+    l.off_lb = o;    o += QT * 4;
+    l.off_lp = o;    o += QT * 4;
+    l.off_misc = o;  o += 64 * 4;
+    l.total = (o + 15) & ~(size_t)15;
+    return l;
+}
+
+// misc slots
+enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_NPOS, M_TOTAL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT,
+       M_DONE, M_THRLO, M_THRHI, M_SCAN0 };
+
+__device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *total) {
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) scr[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < QW; ++w) {
+        uint32_t c = scr[w];
+        pre += (w < wave) ? c : 0u;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+// Bitonic sort of buf[0, cap) ascending (cap a power of two).
+__device__ inline void wg_bitonic(uint64_t *buf, uint32_t cap) {
+    for (uint32_t size = 2; size <= cap; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < cap / 2; i += QT) {
+                uint32_t lo = 2 * i - (i & (stride - 1));
+                uint32_t hi = lo + stride;
+                bool up = ((lo & size) == 0);
+                uint64_t a = buf[lo], b = buf[hi];
+                if ((a > b) == up) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename CellT>
+__global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap);
+    uint64_t *buf = reinterpret_cast<uint64_t *>(lds + lay.off_buf);
+    uint32_t *cnt32 = reinterpret_cast<uint32_t *>(lds + lay.off_cnt);
+    const uint8_t *cnt8 = lds + lay.off_cnt;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(lds + lay.off_hist);
+    uint32_t *pre = reinterpret_cast<uint32_t *>(lds + lay.off_pre);
+    uint32_t *lstart = reinterpret_cast<uint32_t *>(lds + lay.off_start);
+    uint32_t *lb = reinterpret_cast<uint32_t *>(lds + lay.off_lb);
+    uint32_t *lp = reinterpret_cast<uint32_t *>(lds + lay.off_lp);
+    uint32_t *misc = reinterpret_cast<uint32_t *>(lds + lay.off_misc);
+    uint32_t *scr = misc + M_SCAN0;
+
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const uint32_t L = A.L, R = A.R, B = A.B, Bp = A.Bp, k = A.k, cap = A.cap;
+    const uint64_t nbk1 = (1ull << A.nbits) + 1;
+    const uint32_t q0 = (uint32_t)(A.N / B), rem = (uint32_t)(A.N % B);
+    const uint32_t gmax = q0 + (rem ? 1u : 0u);
+    const CellT *cells = static_cast<const CellT *>(A.cells);
+
+    uint64_t q = blockIdx.x;
+    for (;;) {
+        if (A.work) {
+            if (tid == 0) misc[M_Q] = atomicAdd(A.work, 1u);
+            __syncthreads();
+            q = misc[M_Q];
+            __syncthreads();
+        }
+        if (q >= A.nq) break;
+
+        // ---- 1. zero counters and histograms
+        for (uint32_t w = tid; w < lay.cnt_words; w += QT) cnt32[w] = 0u;
+        for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
+
+        // ---- 2. list ranges of the query's L buckets
+        uint32_t len = 0, st = 0;
+        if ((uint32_t)tid < L) {
+            const uint32_t h = A.codes[q * L + tid];
+            const uint32_t *o = A.offsets + (uint64_t)tid * nbk1 + h;
+            st = o[0];
+            len = o[1] - st;
+        }
+        uint32_t total;
+        uint32_t ex = wg_excl_scan(len, scr, &total);
+        if ((uint32_t)tid < L) {
+            pre[tid] = ex;
+            lstart[tid] = st;
+        }
+        if (tid == 0) pre[L] = total;
+        __syncthreads();
+
+        // ---- 3. count: one increment per listed cell per table
+        for (uint32_t idx = tid; idx < total; idx += QT) {
+            uint32_t lo = 0, hi = L;  // largest t with pre[t] <= idx
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (pre[mid] <= idx) lo = mid; else hi = mid;
+            }
+            const uint32_t c = (uint32_t)cells[lstart[lo] + (idx - pre[lo])];
+            atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
+        }
+        __syncthreads();
+
+        if (A.counts_out) {
+            // debug: export counters as [R][B] bytes
+            uint8_t *out = A.counts_out + q * (uint64_t)R * B;
+            for (uint32_t c = tid; c < R * B; c += QT) out[c] = cnt8[(c / B) * Bp + c % B];
+            __syncthreads();
+            if (!A.work) break;
+            q = A.nq;  // unreachable in persistent mode: loop continues via counter
+            continue;
+        }
+
+        // ---- 4. per-repetition histograms of nonzero counts (per-wave copies)
+        {
+            uint32_t *hw = hist + wave * R * (L + 1);
+            for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
+                uint32_t v = cnt32[w];
+                if (!v) continue;
+                const uint32_t r = (4 * w) / Bp;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t cv = (v >> (8 * j)) & 255u;
+                    if (cv) atomicAdd(&hw[r * (L + 1) + cv], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        // fold per-wave copies into copy 0, then suffix sums per repetition
+        for (uint32_t i = tid; i < R * (L + 1); i += QT) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int w = 0; w < QW; ++w) s += hist[w * R * (L + 1) + i];
+            hist[i] = s;
+        }
+        __syncthreads();
+        for (uint32_t r = tid; r < R; r += QT) {
+            uint32_t run = 0;
+            for (int v = (int)L; v >= 1; --v) {
+                run += hist[r * (L + 1) + v];
+                hist[r * (L + 1) + v] = run;  // cells with count >= v
+            }
+            hist[r * (L + 1)] = B;
+        }
+        __syncthreads();
+        // S_r[t] upper bound = cells_r(>= t) * ceil(N/B); minS[t] over r.
+        // Choose the first level: t_hi = max t >= 1 with minS[t] >= k; then the
+        // lowest level <= t_hi whose enumeration stays within the budget.
+        if (tid == 0) {
+            auto minS = [&](uint32_t t) -> uint64_t {
+                uint64_t m = ~0ull;
+                for (uint32_t r = 0; r < R; ++r) {
+                    uint64_t s = (uint64_t)hist[r * (L + 1) + t] * gmax;
+                    m = s < m ? s : m;
+                }
+                return m;
+            };
+            uint32_t thi = 0;
+            for (uint32_t t = L; t >= 1; --t)
+                if (minS(t) >= k) { thi = t; break; }
+            uint32_t level = 0;
+            if (thi >= 1) {
+                level = thi;
+                for (uint32_t t = 1; t <= thi; ++t)
+                    if (minS(t) <= A.budget) { level = t; break; }
+            }
+            misc[M_LEVEL] = level;
+            misc[M_DONE] = 0;
+        }
+        __syncthreads();
+
+        // ---- 5. decode passes
+        for (;;) {
+            if (tid == 0) {
+                uint32_t level = misc[M_LEVEL];
+                uint32_t rep, keep = 0;
+                if (level == 0) {
+                    level = 1;
+                    rep = R - 1;
+                    keep = 1;
+                } else {
+                    uint64_t best = ~0ull;
+                    rep = 0;
+                    for (uint32_t r = 0; r < R; ++r) {
+                        uint64_t s = hist[r * (L + 1) + level];
+                        if (s < best) { best = s; rep = r; }
+                    }
+                    if (level == 1 &&
+                        (uint64_t)hist[(R - 1) * (L + 1) + 1] * gmax <= 2ull * A.budget) {
+                        rep = R - 1;
+                        keep = 1;
+                    }
+                }
+                misc[M_LEVEL] = level;
+                misc[M_REP] = rep;
+                misc[M_KEEPALL] = keep;
+                misc[M_BUFN] = 0;
+                misc[M_NGE] = 0;
+                misc[M_NALL] = 0;
+                misc[M_THRLO] = 0xFFFFFFFFu;
+                misc[M_THRHI] = 0xFFFFFFFFu;
+            }
+            __syncthreads();
+            const uint32_t level = misc[M_LEVEL], rep = misc[M_REP];
+            const bool keep = misc[M_KEEPALL] != 0;
+            const uint32_t *memr = A.mem + (uint64_t)rep * A.N;
+            uint32_t n_ge = 0, n_all = 0;  // per-thread tallies (lane 0 of each wave)
+
+            for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
+                const uint32_t b = cb0 + tid;
+                uint32_t cval = 0;
+                if (b < B) cval = cnt8[rep * Bp + b];
+                const bool pos = (b < B) && (cval >= level);
+                const uint32_t sz = pos ? (q0 + (b < rem ? 1u : 0u)) : 0u;
+                uint32_t npos, tsz;
+                const uint32_t ci = wg_excl_scan(pos ? 1u : 0u, scr, &npos);
+                const uint32_t ps = wg_excl_scan(sz, scr, &tsz);
+                if (pos) {
+                    lb[ci] = b;
+                    lp[ci] = ps;
+                }
+                __syncthreads();
+                for (uint32_t off = 0; off < tsz; off += QT) {
+                    const uint32_t idx = off + tid;
+                    bool take = false;
+                    uint64_t key = 0;
+                    bool ge = false;
+                    if (idx < tsz) {
+                        uint32_t lo = 0, hi = npos;
+                        while (hi - lo > 1) {
+                            uint32_t mid = (lo + hi) >> 1;
+                            if (lp[mid] <= idx) lo = mid; else hi = mid;
+                        }
+                        const uint32_t bb = lb[lo];
+                        const uint32_t x = memr[(uint64_t)bb * q0 + (bb < rem ? bb : rem) + (idx - lp[lo])];
+                        const uint16_t *gx = A.grp + (uint64_t)x * A.Rp;
+                        uint32_t m = 0xFFFFFFFFu, cs = 0;
+                        for (uint32_t r = 0; r < R; ++r) {
+                            const uint32_t c = r * Bp + gx[r];
+                            const uint32_t v = cnt8[c];
+                            if (v <= m) {  // later repetitions have larger cell ids
+                                m = v;
+                                cs = c;
+                            }
+                        }
+                        ge = m >= level;
+                        take = keep || ge;
+                        key = ((uint64_t)(255u - m) << 56) | ((uint64_t)cs << 32) | x;
+                        if (take) {
+                            const uint64_t thr = ((uint64_t)misc[M_THRHI] << 32) | misc[M_THRLO];
+                            if (key < thr) {
+                                const uint32_t slot = atomicAdd(&misc[M_BUFN], 1u);
+                                buf[slot] = key;
+                            }
+                        }
+                    }
+                    const unsigned long long mg = __ballot(take && ge);
+                    const unsigned long long ma = __ballot(take);
+                    if (lane == 0) {
+                        n_ge += __popcll(mg);
+                        n_all += __popcll(ma);
+                    }
+                    __syncthreads();
+                    if (misc[M_BUFN] > cap - QT) {
+                        // merge: sort, keep the k smallest, tighten the threshold
+                        const uint32_t nb = misc[M_BUFN];
+                        for (uint32_t i = nb + tid; i < cap; i += QT) buf[i] = ~0ull;
+                        __syncthreads();
+                        wg_bitonic(buf, cap);
+                        if (tid == 0) {
+                            const uint32_t keepn = nb < k ? nb : k;
+                            misc[M_BUFN] = keepn;
+                            if (keepn == k) {
+                                misc[M_THRLO] = (uint32_t)buf[k - 1];
+                                misc[M_THRHI] = (uint32_t)(buf[k - 1] >> 32);
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+            // pass totals
+            if (lane == 0) {
+                atomicAdd(&misc[M_NGE], n_ge);
+                atomicAdd(&misc[M_NALL], n_all);
+            }
+            __syncthreads();
+            {
+                const uint32_t nb = misc[M_BUFN];
+                for (uint32_t i = nb + tid; i < cap; i += QT) buf[i] = ~0ull;
+            }
+            __syncthreads();
+            wg_bitonic(buf, cap);
+            const uint32_t nge = misc[M_NGE], nall = misc[M_NALL];
+            const bool ok = nge >= k;
+            if (ok || keep) {
+                // emit the buffered keys (and, for the fill path, zero cells)
+                const uint32_t nres = (nall < k ? nall : k);
+                uint32_t *oid = A.ids + q * (uint64_t)k;
+                uint32_t *osc = A.scores ? A.scores + q * (uint64_t)k : nullptr;
+                for (uint32_t i = tid; i < nres; i += QT) {
+                    const uint64_t key = buf[i];
+                    oid[i] = (uint32_t)key;
+                    if (osc) osc[i] = 255u - (uint32_t)(key >> 56);
+                }
+                if (!ok && nres < k && wave == 0) {
+                    // zero fill from repetition R-1, cells ascending, ids ascending
+                    uint32_t need = k - nres, outp = nres;
+                    const uint32_t *memz = A.mem + (uint64_t)(R - 1) * A.N;
+                    for (uint32_t b0 = 0; b0 < B && need; b0 += 64) {
+                        const uint32_t b = b0 + lane;
+                        const bool z = (b < B) && (cnt8[(R - 1) * Bp + b] == 0);
+                        unsigned long long zm = __ballot(z);
+                        while (zm && need) {
+                            const uint32_t bb = b0 + (uint32_t)(__ffsll((long long)zm) - 1);
+                            zm &= zm - 1;
+                            const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
+                            const uint32_t takeN = sz < need ? sz : need;
+                            const uint64_t mo = (uint64_t)bb * q0 + (bb < rem ? bb : rem);
+                            for (uint32_t j = lane; j < takeN; j += 64) {
+                                oid[outp + j] = memz[mo + j];
+                                if (osc) osc[outp + j] = 0u;
+                            }
+                            outp += takeN;
+                            need -= takeN;
+                        }
+                    }
+                    for (uint32_t j = outp + lane; j < k; j += 64) {
+                        oid[j] = 0xFFFFFFFFu;
+                        if (osc) osc[j] = 0u;
+                    }
+                }
+                if (tid == 0) misc[M_DONE] = 1;
+            } else if (tid == 0) {
+                // lower the level: the lowest level whose minimum enumeration
+                // stays within 8x the larger of the budget and this pass
+                const uint32_t lv = misc[M_LEVEL];
+                uint64_t lim = 8ull * (A.budget > nall ? A.budget : nall);
+                uint32_t next = lv - 1;
+                for (uint32_t t = 1; t < lv; ++t) {
+                    uint64_t m = ~0ull;
+                    for (uint32_t r = 0; r < R; ++r) {
+                        uint64_t s = (uint64_t)hist[r * (L + 1) + t] * gmax;
+                        m = s < m ? s : m;
+                    }
+                    if (m <= lim) { next = t; break; }
+                }
+                misc[M_LEVEL] = next;  // 0 selects the fill path
+            }
+            __syncthreads();
+            if (misc[M_DONE]) break;
+        }
+        __syncthreads();
+        if (!A.work) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+uint32_t query_max_k() { return 4096; }
+
+static uint32_t cap_for(uint32_t k) {
+    uint32_t need = std::max<uint32_t>(512u, k + QT);
+    uint32_t c = 1;
+    while (c < need) c <<= 1;
+    return c;
+}
+
+size_t query_lds_bytes(const Index &ix, uint32_t k) {
+    uint32_t Bp = (ix.p.B + 3) & ~3u;
+    return q_layout(ix.p.L, ix.p.R, Bp, cap_for(k)).total;
+}
+
+static int max_lds() {
+    static int v = 0;
+    if (!v) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int x = 0;
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || x <= 0)
+            x = 65536;
+        v = x;
+    }
+    return v;
+}
+
+static int num_cus() {
+    static int v = 0;
+    if (!v) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int x = 0;
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || x <= 0)
+            x = 256;
+        v = x;
+    }
+    return v;
+}
+
+template <typename CellT>
+static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
+        attr_set = true;
+    }
+    uint64_t grid = a.nq;
+    if (persistent) {
+        const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)(160 * 1024) / std::max<size_t>(lds, 1)));
+        grid = std::min<uint64_t>(a.nq, per_cu * (uint64_t)num_cus());
+    }
+    if (grid == 0) return;
+    if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
+    hipLaunchKernelGGL(query_kernel<CellT>, dim3((unsigned)grid), dim3(QT), lds, s, a);
+    FL_CHECK_LAUNCH();
+}
+
+static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint32_t k) {
+    QArgs a{};
+    a.codes = codes;
+    a.nq = nq;
+    a.offsets = ix.offsets;
+    a.cells = ix.cells;
+    a.grp = ix.grp;
+    a.mem = ix.mem;
+    a.N = ix.N;
+    a.L = ix.p.L;
+    a.R = ix.p.R;
+    a.Rp = ix.Rp;
+    a.B = ix.p.B;
+    a.Bp = (ix.p.B + 3) & ~3u;
+    a.nbits = ix.nbits;
+    a.k = k;
+    a.cap = cap_for(k);
+    a.budget = BUDGET;
+    return a;
+}
+
+void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint32_t k,
+                  uint32_t *ids_dev, uint32_t *scores_dev, bool persistent, hipStream_t s,
+                  uint32_t *work_counter) {
+    if (nq == 0) return;
+    QArgs a = make_args(ix, codes_dev, nq, k);
+    a.ids = ids_dev;
+    a.scores = scores_dev;
+    a.work = persistent ? work_counter : nullptr;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap).total;
+    if ((int)lds > max_lds())
+        fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +
+                                " bytes) exceeds the workgroup LDS limit; reduce B*R or k");
+    if (persistent) FL_HIP(hipMemsetAsync(work_counter, 0, 4, s));
+    if (ix.cell_bytes == 2)
+        launch_q<uint16_t>(a, lds, persistent, s);
+    else
+        launch_q<uint32_t>(a, lds, persistent, s);
+}
+
+void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint8_t *counts_dev,
+                   hipStream_t s) {
+    if (nq == 0) return;
+    QArgs a = make_args(ix, codes_dev, nq, 1);
+    a.counts_out = counts_dev;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap).total;
+    if ((int)lds > max_lds()) fail(FLINNG_EINVAL, "per-query state exceeds the LDS limit");
+    if (ix.cell_bytes == 2)
+        launch_q<uint16_t>(a, lds, false, s);
+    else
+        launch_q<uint32_t>(a, lds, false, s);
+}
+
+}  // namespace flinng

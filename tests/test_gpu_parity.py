@@ -1,0 +1,177 @@
+"""GPU parity: the HIP library, called through its C ABI, against the CPU
+oracle on the same seeded inputs, layer by layer and bit-exact: hash codes,
+the exported index (groups and reverse-index lists), per-cell counts, and the
+decoded ids and scores.  Sizes span several tiles and ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import build_both, log, oracle_query, random_sets, scaled, subset_sets
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2106_11565_amd as flinng
+    flinng.lib()
+    return flinng
+
+
+# --------------------------------------------------------------------------
+# hash codes
+
+@pytest.mark.parametrize("family", [0, 1])
+@pytest.mark.parametrize("n,d,K,L", [(1, 1, 1, 1), (77, 7, 5, 3), (300, 33, 13, 7),
+                                     (513, 130, 8, 4), (1000, 256, 16, 9)])
+def test_srp_codes_random_shapes(fl, family, n, d, K, L):
+    log("srp codes", family, n, d, K, L)
+    rng = np.random.default_rng(n * 131 + d)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    if family == 1:
+        x = synth.f32_to_bf16(x)
+    B = max(1, n // 4)
+    gi = fl.Index(x, family, K, L, 2, B, seed=1234)
+    w = oracle.hyperplanes(1234, K * L, d)
+    xd = oracle.bf16_to_f64(x) if family == 1 else x.astype(np.float64)
+    want = oracle.srp_codes(xd, 1234, K, L, w=w)
+    got = gi.debug_hash(x)
+    assert np.array_equal(got, want)
+
+
+def test_srp_exact_zero_and_tiny_projections(fl):
+    """Rows built so that some projections are exactly 0 or +-2^-60: the GPU
+    flags them (|P| under its bound), rechecks in FP64 and falls back to the
+    exact sum; the bits must equal the exact rational signs."""
+    K, L, d, seed = 8, 4, 64, 77
+    w = oracle.hyperplanes(seed, K * L, d)
+    rng = np.random.default_rng(5)
+    rows = [rng.standard_normal(d).astype(np.float32) for _ in range(40)]
+    for h in range(K * L):
+        nz = np.nonzero(w[h])[0]
+        i, j, k_ = nz[0], nz[1], nz[2]
+        z = np.zeros(d, dtype=np.float32)
+        z[i], z[j] = w[h, j], -w[h, i]        # exactly orthogonal to w[h]
+        rows.append(z.copy())
+        t = z.copy()
+        t[k_] = np.float32(2.0**-60 / w[h, k_])   # projection exactly +2^-60
+        rows.append(t)
+        rows.append(-t)
+    x = np.stack(rows).astype(np.float32)
+    want = oracle.srp_codes(x.astype(np.float64), seed, K, L, w=w)
+    gi = fl.Index(x, 0, K, L, 3, 10, seed=seed)
+    assert np.array_equal(gi.debug_hash(x), want)
+    assert gi.info.srp_rechecked > 0 and gi.info.srp_exact > 0
+    log("rechecked", gi.info.srp_rechecked, "exact", gi.info.srp_exact)
+
+
+@pytest.mark.parametrize("family", [2, 3])
+@pytest.mark.parametrize("K,L,b,mean", [(1, 1, 1, 3), (2, 32, 20, 81), (3, 48, 22, 68),
+                                        (4, 5, 12, 300), (1, 200, 16, 10), (7, 3, 24, 1000)])
+def test_minhash_codes_random(fl, family, K, L, b, mean):
+    log("minhash codes", family, K, L, b, mean)
+    rng = np.random.default_rng(K * 1000 + L + b)
+    dt = np.uint64 if family == 3 else np.uint32
+    items, offs = random_sets(rng, 150, mean, dt)
+    gi = fl.Index((items, offs), family, K, L, 2, 10, seed=99, bucket_bits=b)
+    want = oracle.minhash_codes(items.astype(np.uint64), offs, 99, K, L, b)
+    assert np.array_equal(gi.debug_hash((items, offs)), want)
+
+
+# --------------------------------------------------------------------------
+# whole pipeline on the workloads (scaled where the oracle needs it)
+
+def _check_all(fl, family, data, q, K, L, R, B, seed, bucket_bits, ks=(1, 10, 37)):
+    gi, oi = build_both(fl, family, data, K, L, R, B, seed, bucket_bits)
+    log("built", family, "N", oi.N, "entries", gi.info.list_entries)
+    # index
+    offs, cells, groups = gi.export()
+    assert np.array_equal(groups, oi.g)
+    assert np.array_equal(offs, oi.offsets)
+    assert np.array_equal(cells, oi.cells)
+    # codes and counts
+    assert np.array_equal(gi.debug_hash(q), oi.hash(q))
+    cnt = gi.debug_counts(q)
+    assert np.array_equal(cnt, oi.counts(oi.hash(q)))
+    # ids and scores, one workgroup per query and persistent
+    for k in ks:
+        want_i, want_s = oracle_query(oi, q, k)
+        for pers in (False, True):
+            got_i, got_s = gi.query(q, k, persistent=pers)
+            bad = np.nonzero(np.any(got_i != want_i, axis=1))[0]
+            assert len(bad) == 0, (k, pers, bad[:5], got_i[bad[:2]], want_i[bad[:2]],
+                                   got_s[bad[:2]], want_s[bad[:2]])
+            assert np.array_equal(got_s, want_s)
+    return gi, oi
+
+
+def test_c1_dense_gmm_full(fl):
+    cfg, X, Q, _ = scaled("c1", 1.0, 100)
+    _check_all(fl, 0, X, Q, cfg["K"], cfg["L"], cfg["R"], cfg["B"], 5, 0)
+
+
+def test_c2_genome_scaled(fl):
+    cfg, (it, of), (qit, qof), _ = scaled("c2", 0.01, 120)
+    _check_all(fl, 3, (it, of), (qit, qof), cfg["K"], cfg["L"], cfg["R"], cfg["B"], 6,
+               cfg["bucket_bits"])
+
+
+def test_c3_relu_scaled(fl):
+    cfg, X, Q, _ = scaled("c3", 0.006, 60)
+    _check_all(fl, 1, X, Q, cfg["K"], cfg["L"], cfg["R"], cfg["B"], 7, 0, ks=(1, 10))
+
+
+def test_c4_url_scaled(fl):
+    cfg, (it, of), (qit, qof), _ = scaled("c4", 0.002, 150)
+    _check_all(fl, 2, (it, of), (qit, qof), cfg["K"], cfg["L"], cfg["R"], cfg["B"], 8, 18)
+
+
+# --------------------------------------------------------------------------
+# degenerate cases of the method
+
+@pytest.mark.parametrize("R,B,L,k", [(3, 1, 4, 7), (1, 9, 3, 50), (4, 5, 1, 12),
+                                     (2, 50, 6, 500), (16, 7, 2, 3)])
+def test_degenerate_grids(fl, R, B, L, k):
+    log("degenerate", R, B, L, k)
+    X, Q, _ = synth.dense_gmm(N=300, d=24, n_centres=12, nq=40)
+    _check_all(fl, 0, X, Q, 6, L, R, B, 11, 0, ks=(k,))
+
+
+def test_identical_queries_returned_with_full_score(fl):
+    X, _, _ = synth.dense_gmm(N=5000, d=64, n_centres=200, sigma=0.05, nq=1)
+    gi = fl.Index(X, 0, 12, 16, 3, 250, seed=3)
+    sel = np.arange(0, 5000, 97)
+    ids, sc = gi.query(X[sel], 10)
+    for i, x in enumerate(sel):
+        row = list(ids[i])
+        assert x in row and sc[i][row.index(x)] == 16
+
+
+def test_large_k_and_ragged(fl):
+    cfg, (it, of), (qit, qof), _ = scaled("c2", 0.002, 33)
+    gi, oi = build_both(fl, 3, (it, of), 2, 8, 3, 17, 13, 12)
+    for k in (1000, oi.N, oi.N + 5):
+        if k > 4096:
+            continue
+        want = oracle_query(oi, (qit, qof), k)
+        got = gi.query((qit, qof), k)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def test_errors(fl):
+    X, _, _ = synth.dense_gmm(N=50, d=8, n_centres=3, nq=1)
+    with pytest.raises(fl.FlinngError) as e:
+        fl.Index(X, 0, 4, 3, 2, 51, seed=1)      # B > N
+    assert e.value.code == fl.EINVAL
+    with pytest.raises(fl.FlinngError):
+        fl.Index(X, 0, 0, 3, 2, 5, seed=1)       # K = 0
+    with pytest.raises(fl.FlinngError):
+        fl.Index(X, 0, 4, 256, 2, 5, seed=1)     # L > 255
+    gi = fl.Index(X, 0, 4, 3, 2, 5, seed=1)
+    with pytest.raises(fl.FlinngError):
+        gi.query(X[:3], 0)
+    with pytest.raises(fl.FlinngError):
+        gi.query(X[:3], 5000)

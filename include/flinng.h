@@ -9,7 +9,7 @@
  * distance-sensitive Bloom filter (Section 3, Theorem 1) built from L shared
  * LSH functions, each the concatenation of K hashes (Section 3, concatenation
  * trick).  The filters are stored as one reverse index per LSH function:
- * bucket value -> list of cells (Section 5, Implementation).  A query counts,
+ * bucket value -> list of cells (Section 6, Implementation).  A query counts,
  * for every cell, in how many tables it collides, then decodes by threshold
  * relaxation (Algorithm 3, equivalent to Algorithm 2 at decreasing
  * thresholds) and returns k point ids.
@@ -100,7 +100,7 @@ typedef struct flinng_index_info {
 
 /*
  * flinng_build -- one-pass index construction (Algorithm 1 plus the reverse
- * index of Section 5).
+ * index of Section 6).
  *  p      (host)  parameters; validated (FLINNG_EINVAL on any violation,
  *                 including B > N, dense dim mismatch, L*K*dim overflow).
  *  data   (host struct) the N points; values/offsets on host or device per
@@ -115,7 +115,7 @@ int flinng_build(const flinng_params *p, const flinng_input *data,
 
 /*
  * flinng_query -- batched query: hash, count per cell through the reverse
- * index (Section 5), decode by threshold relaxation (Algorithm 3).
+ * index (Section 6), decode by threshold relaxation (Algorithm 3).
  *  q        (host struct) nq = q->count queries of the index's family.
  *  k        neighbours per query, 1..4096.
  *  ids      (host or device per out_on_device) nq*k uint32, row-major:
@@ -134,6 +134,21 @@ int flinng_build(const flinng_params *p, const flinng_input *data,
 int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
                  uint32_t *ids, uint32_t *scores, uint32_t out_on_device,
                  uint32_t persistent, void *stream);
+
+/*
+ * flinng_query_codes -- the count + threshold + decode stage alone, for
+ * bucket codes already on the device (as flinng_debug_hash produces them).
+ *  codes   (device) nq*L uint32, row-major, each < 2^bucket_bits.
+ *  ids, scores  (device) nq*k uint32 as in flinng_query (scores may be NULL).
+ *  stats   (device, optional) 4 uint64 that the launch adds to: reverse-index
+ *          list entries read, candidates enumerated over all decode passes,
+ *          candidates of the final passes, decode passes.  The caller zeroes
+ *          them.
+ * Returns once the work is enqueued on `stream`.
+ */
+int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t nq,
+                       uint32_t k, uint32_t *ids, uint32_t *scores,
+                       uint32_t persistent, uint64_t *stats, void *stream);
 
 /* Release an index and all its device memory (NULL is allowed). */
 void flinng_index_free(flinng_index *idx);

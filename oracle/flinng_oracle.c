@@ -148,7 +148,7 @@ int or_exact_dot_sign(const double *x, const double *w, uint32_t d)
 
 /* ------------------------------------------------------------------------- */
 /* MinHash for item sets (the set-similarity LSH instance; the paper hashes
- * genome n-gram sets with MinHash, Section 6 "Datasets").
+ * genome n-gram sets with MinHash, Section 7, Experiments, "Datasets").
  *   a[t][j]  = sm64(key_MH, t*K + j)
  *   pi_tj(e) = mix64(e XOR a[t][j]) >> 32           (top 32 bits)
  *   mh_tj(S) = min over e in S of pi_tj(e)          (empty set: 0xFFFFFFFF)
@@ -247,7 +247,7 @@ void or_members(const uint32_t *g, uint64_t N, uint32_t R, uint32_t B,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Reverse index (Section 5, Implementation): for every table t, a map from a
+/* Reverse index (Section 6, Implementation): for every table t, a map from a
  * bucket value to the list of cells whose distance-sensitive Bloom filter has
  * that bucket set.  A cell c = r*B + b holds bucket h of table t iff some
  * member x of group (r, b) has bucket_t(x) = h.  Lists are sets (a Bloom
@@ -297,7 +297,7 @@ int64_t or_build_lists(const uint32_t *codes, const uint32_t *g, uint64_t N,
     return (int64_t)total;
 }
 
-/* Cell collision counts through the reverse index (Section 5): for each table
+/* Cell collision counts through the reverse index (Section 6): for each table
  * the query's bucket list adds one to every listed cell.                    */
 void or_counts(const uint64_t *offsets, const uint32_t *cells, uint32_t L,
                uint32_t nbits, uint32_t ncells, const uint32_t *qcodes,

@@ -72,6 +72,7 @@ def lib():
         sig = {
             "flinng_build": (ctypes.c_int, [P(Params), P(Input), c_vp, P(c_vp)]),
             "flinng_query": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_u32, c_vp]),
+            "flinng_query_codes": (ctypes.c_int, [c_vp, c_vp, c_u64, c_u32, c_vp, c_vp, c_u32, c_vp, c_vp]),
             "flinng_index_free": (None, [c_vp]),
             "flinng_index_get_info": (ctypes.c_int, [c_vp, P(IndexInfo)]),
             "flinng_last_error": (ctypes.c_char_p, []),

@@ -244,6 +244,22 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uin
     });
 }
 
+int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t nq, uint32_t k,
+                       uint32_t *ids, uint32_t *scores, uint32_t persistent, uint64_t *stats,
+                       void *stream) {
+    return guard([&] {
+        require(idx && codes && ids, "NULL argument");
+        require(k >= 1 && k <= query_max_k(), "k must be in 1..4096");
+        if (nq == 0) return;
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf work(persistent ? 4 : 0, s);
+        query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>(),
+                     reinterpret_cast<unsigned long long *>(stats));
+    });
+}
+
 int flinng_debug_hash(const flinng_index *idx, const flinng_input *q, uint32_t *codes,
                       uint32_t out_on_device, void *stream) {
     return guard([&] {

@@ -1,5 +1,5 @@
 // One-pass index build on gfx950 (Algorithm 1 and the reverse index of
-// Section 5).
+// Section 6, Implementation).
 //
 // Groups: repetition r permutes the points with a keyed bijection P_r of
 // [0, N) and point x joins group P_r(x) mod B (Algorithm 1: a random
@@ -38,8 +38,7 @@ struct GroupKeys {
     uint64_t k[16][4];
 };
 
-// grp[x*Rp + r] = P_r(x) mod B; also emits (group, x) for repetition `rsel`
-// so the members of each cell can be sorted by id.
+// grp[x*Rp + r] = P_r(x) mod B (padding repetitions R..Rp-1 hold 0).
 __global__ void groups_kernel(uint64_t N, uint32_t R, uint32_t Rp, uint32_t B, uint32_t half,
                               GroupKeys gk, uint16_t *__restrict__ grp) {
     const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -132,7 +132,8 @@ void build_lists(Index &ix, const uint32_t *codes_dev, hipStream_t s);
 // Query (query.hip).
 void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
                   uint32_t k, uint32_t *ids_dev, uint32_t *scores_dev,
-                  bool persistent, hipStream_t s, uint32_t *work_counter);
+                  bool persistent, hipStream_t s, uint32_t *work_counter,
+                  unsigned long long *stats = nullptr);
 void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
                    uint8_t *counts_dev, hipStream_t s);
 size_t query_lds_bytes(const Index &ix, uint32_t k);

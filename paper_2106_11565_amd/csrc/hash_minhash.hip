@@ -1,7 +1,7 @@
 // MinHash hashing of item sets on gfx950.
 //
 // The set-similarity LSH instance (the paper hashes genome n-gram sets with
-// MinHash, Section 6, Datasets; the concatenation trick of Section 3 joins K
+// MinHash, Section 7, Experiments, "Datasets"; the concatenation trick of Section 3 joins K
 // minima per table):
 //   a[t][j]  = sm64(key_MH, t*K + j)
 //   pi_tj(e) = top 32 bits of splitmix_finalize(e XOR a[t][j])

@@ -4,7 +4,7 @@
 // concatenation trick): bit j of table t is 1 iff the exact dot product of
 // the row with hyperplane h = t*K + j is positive (an exact zero gives 0);
 // the table's bucket is sum_j bit_j 2^j.  Hashing is shared by every filter
-// and done once per point or query (Section 5, Implementation).
+// and done once per point or query (Section 6, Implementation).
 //
 // Pipeline (one batch of n rows, H = L*K hyperplanes):
 //   1. prep: bf16 operand planes (fp32 rows split exactly into 3 bf16 terms)

@@ -4,7 +4,7 @@
 // from a device counter).  All per-query state lives in LDS:
 //   * the B*R cell counters as bytes (count <= L <= 255), 4 per dword,
 //     incremented with 32-bit LDS atomics while the workgroup walks the L
-//     reverse-index lists selected by the query's codes (Section 5: count how
+//     reverse-index lists selected by the query's codes (Section 6: count how
 //     often each cell collides with the query);
 //   * per-repetition histograms of the nonzero counts;
 //   * a top-k key buffer.
@@ -48,6 +48,9 @@ struct QArgs {
     uint8_t *counts_out;   // debug: write counters and skip decode
     uint32_t *work;        // persistent: next query counter (nullptr: 1 WG/query)
     uint32_t budget;
+    unsigned long long *stats;  // optional per-launch totals: list entries read,
+                                // candidates enumerated (all passes), candidates
+                                // of the final pass, passes
 };
 
 struct QLayout {
@@ -252,6 +255,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         __syncthreads();
 
         // ---- 5. decode passes
+        unsigned long long st_all = 0, st_final = 0, st_passes = 0;  // tid 0 only
         for (;;) {
             if (tid == 0) {
                 uint32_t level = misc[M_LEVEL];
@@ -287,6 +291,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             const bool keep = misc[M_KEEPALL] != 0;
             const uint32_t *memr = A.mem + (uint64_t)rep * A.N;
             uint32_t n_ge = 0, n_all = 0;  // per-thread tallies (lane 0 of each wave)
+            unsigned long long pass_members = 0;
 
             for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
                 const uint32_t b = cb0 + tid;
@@ -301,6 +306,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                     lb[ci] = b;
                     lp[ci] = ps;
                 }
+                pass_members += tsz;
                 __syncthreads();
                 for (uint32_t off = 0; off < tsz; off += QT) {
                     const uint32_t idx = off + tid;
@@ -376,6 +382,9 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             wg_bitonic(buf, cap);
             const uint32_t nge = misc[M_NGE], nall = misc[M_NALL];
             const bool ok = nge >= k;
+            st_all += pass_members;
+            st_passes += 1;
+            if (ok || keep) st_final = pass_members;
             if (ok || keep) {
                 // emit the buffered keys (and, for the fill path, zero cells)
                 const uint32_t nres = (nall < k ? nall : k);
@@ -432,6 +441,12 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             }
             __syncthreads();
             if (misc[M_DONE]) break;
+        }
+        if (A.stats && tid == 0) {
+            atomicAdd(&A.stats[0], (unsigned long long)total);
+            atomicAdd(&A.stats[1], st_all);
+            atomicAdd(&A.stats[2], st_final);
+            atomicAdd(&A.stats[3], st_passes);
         }
         __syncthreads();
         if (!A.work) break;
@@ -521,12 +536,13 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
 
 void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint32_t k,
                   uint32_t *ids_dev, uint32_t *scores_dev, bool persistent, hipStream_t s,
-                  uint32_t *work_counter) {
+                  uint32_t *work_counter, unsigned long long *stats) {
     if (nq == 0) return;
     QArgs a = make_args(ix, codes_dev, nq, k);
     a.ids = ids_dev;
     a.scores = scores_dev;
     a.work = persistent ? work_counter : nullptr;
+    a.stats = stats;
     const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap).total;
     if ((int)lds > max_lds())
         fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +

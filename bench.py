@@ -156,23 +156,24 @@ def main():
 
     hash_ms = timed(hash_once, args.steps)
     decode_ms = timed(decode_once, args.steps)
-    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
     decode_once(stats)
     torch.cuda.synchronize()
     st = [int(v) for v in stats.cpu().tolist()]
     assert np.array_equal(ids_d.cpu().numpy().view(np.uint32), plain_ids), "decode-only != full path"
     # algorithmic bytes of one decode launch: codes (L*4) and bucket offset
-    # pairs (L*8) per query, every list entry read, the member id plus the R
-    # group ids of each candidate of the final decode pass, k ids + scores out
+    # pairs (L*8) per query, every list entry read, each member id read by the
+    # final decode pass (4 B), the R group ids of each candidate it gathers
+    # (2R B), and k ids + scores out
     cb = info.cell_id_bytes
-    alg_bytes = nq * L * 12 + st[0] * cb + st[2] * (4 + 2 * R) + nq * k * 8
+    alg_bytes = nq * L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * R + nq * k * 8
     achieved = alg_bytes / (decode_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "query_kernel (count + threshold + decode)",
             "alg_bytes_per_launch": int(alg_bytes), "launch_ms": round(decode_ms, 4),
-            "list_entries": st[0], "candidates_all_passes": st[1],
-            "candidates_final": st[2], "passes": st[3]}
+            "list_entries": st[0], "member_ids_all_passes": st[1],
+            "member_ids_final": st[2], "passes": st[3], "group_rows_gathered": st[4]}
     log(f"hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg_bytes / 1e6:.1f} MB "
         f"-> {achieved:.0f} GB/s; stats {st}")
 

@@ -140,10 +140,10 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
  * bucket codes already on the device (as flinng_debug_hash produces them).
  *  codes   (device) nq*L uint32, row-major, each < 2^bucket_bits.
  *  ids, scores  (device) nq*k uint32 as in flinng_query (scores may be NULL).
- *  stats   (device, optional) 4 uint64 that the launch adds to: reverse-index
- *          list entries read, candidates enumerated over all decode passes,
- *          candidates of the final passes, decode passes.  The caller zeroes
- *          them.
+ *  stats   (device, optional) 5 uint64 that the launch adds to: reverse-index
+ *          list entries read, cell member ids read over all decode passes,
+ *          member ids read in the final passes, decode passes, and candidate
+ *          group rows gathered in the final passes.  The caller zeroes them.
  * Returns once the work is enqueued on `stream`.
  */
 int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t nq,

@@ -108,6 +108,7 @@ static void free_index(Index *ix) {
     if (ix->cells) (void)hipFree(ix->cells);
     if (ix->grp) (void)hipFree(ix->grp);
     if (ix->mem) (void)hipFree(ix->mem);
+    if (ix->cmg) (void)hipFree(ix->cmg);
     if (ix->hyp) (void)hipFree(ix->hyp);
     if (ix->hypnorm) (void)hipFree(ix->hypnorm);
     delete ix;
@@ -160,7 +161,10 @@ int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
             uint64_t bytes = 0;
             ix->offsets = dmalloc<uint32_t>((uint64_t)p->L * (nbk + 1), bytes);
             ix->grp = dmalloc<uint16_t>(N * ix->Rp, bytes);
-            ix->mem = dmalloc<uint32_t>(N * p->R, bytes);
+            const uint64_t gmax = (N + p->B - 1) / p->B;
+            ix->mstride = (uint32_t)((gmax + 3) & ~3ull);
+            ix->mem = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
+            ix->cmg = dmalloc<uint16_t>((uint64_t)p->R * p->B * ix->mstride * ix->Rp, bytes);
             if (dense) {
                 ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
                 ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);

@@ -60,6 +60,30 @@ __global__ void member_keys_kernel(const uint16_t *__restrict__ grp, uint64_t N,
     vals[x] = (uint32_t)x;
 }
 
+// sorted position p of group b = keys[p] sits at run offset
+// p - (b*floor(N/B) + min(b, N mod B)); copy it to slot b*mstride + that.
+__global__ void member_slots_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ids,
+                                    uint64_t N, uint32_t B, uint32_t mstride,
+                                    uint32_t *__restrict__ mem) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const uint64_t b = keys[p];
+    const uint64_t q0 = N / B, rem = N % B;
+    const uint64_t run = b * q0 + (b < rem ? b : rem);
+    mem[b * mstride + (p - run)] = ids[p];
+}
+
+// cmg[slot][r] = group in repetition r of the member stored in mem[slot]
+// (zeros for the padding slots).
+__global__ void cell_groups_kernel(const uint32_t *__restrict__ mem, const uint16_t *__restrict__ grp,
+                                   uint64_t nslots, uint32_t Rp, uint16_t *__restrict__ cmg) {
+    const uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslots) return;
+    const uint32_t x = mem[sl];
+    for (uint32_t r = 0; r < Rp; ++r)
+        cmg[sl * Rp + r] = (x == 0xFFFFFFFFu) ? (uint16_t)0 : grp[(uint64_t)x * Rp + r];
+}
+
 void build_groups(Index &ix, hipStream_t s) {
     const uint64_t N = ix.N;
     const uint32_t R = ix.p.R, B = ix.p.B;
@@ -73,17 +97,27 @@ void build_groups(Index &ix, hipStream_t s) {
     hipLaunchKernelGGL(groups_kernel, dim3(grid), dim3(256), 0, s, N, R, ix.Rp, B, nb / 2, gk,
                        ix.grp);
     FL_CHECK_LAUNCH();
-    // members of each cell, ascending id: stable sort of ids by group
-    DevBuf k1(N * 8, s), k2(N * 8, s), v2(N * 4, s);
+    // members of each cell, ascending id: stable sort of ids by group, then
+    // each group's run (at b*floor(N/B) + min(b, N mod B)) moves to its
+    // 16-byte aligned slot b*mstride; unused slot tails hold 0xFFFFFFFF
+    DevBuf k1(N * 8, s), k2(N * 8, s), v1(N * 4, s), v2(N * 4, s);
     int gbits = 1;
     while ((1u << gbits) < B) ++gbits;
+    FL_HIP(hipMemsetAsync(ix.mem, 0xFF, (size_t)R * B * ix.mstride * 4, s));
     for (uint32_t r = 0; r < R; ++r) {
-        uint32_t *vr = ix.mem + (uint64_t)r * N;
         hipLaunchKernelGGL(member_keys_kernel, dim3(grid), dim3(256), 0, s, ix.grp, N, ix.Rp, r,
-                           k1.as<uint64_t>(), vr);
+                           k1.as<uint64_t>(), v1.as<uint32_t>());
         FL_CHECK_LAUNCH();
-        radix_sort_u64(k1.as<uint64_t>(), k2.as<uint64_t>(), vr, v2.as<uint32_t>(), N, gbits, s);
+        radix_sort_u64(k1.as<uint64_t>(), k2.as<uint64_t>(), v1.as<uint32_t>(), v2.as<uint32_t>(),
+                       N, gbits, s);
+        hipLaunchKernelGGL(member_slots_kernel, dim3(grid), dim3(256), 0, s, k1.as<uint64_t>(),
+                           v1.as<uint32_t>(), N, B, ix.mstride, ix.mem + (uint64_t)r * B * ix.mstride);
+        FL_CHECK_LAUNCH();
     }
+    const uint64_t nslots = (uint64_t)R * B * ix.mstride;
+    hipLaunchKernelGGL(cell_groups_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s,
+                       ix.mem, ix.grp, nslots, ix.Rp, ix.cmg);
+    FL_CHECK_LAUNCH();
 }
 
 // ---------------------------------------------------------------------------

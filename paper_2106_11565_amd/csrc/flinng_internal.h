@@ -54,8 +54,12 @@ __host__ __device__ inline uint64_t sm64(uint64_t s, uint64_t i) {
 //   grp       [N][Rp]         uint16 group of point x in repetition r
 //             (Rp = R rounded up to a power of two; point-major so one
 //             vector load gathers all R groups of a candidate)
-//   mem       [R][N]          uint32 members of cell (r,b) at
-//             [b*floor(N/B) + min(b, N mod B), +size), ascending id
+//   mem       [R][B][mstride] uint32 members of cell (r,b), ascending id,
+//             padded with 0xFFFFFFFF to mstride = ceil(N/B) rounded up to 4,
+//             so every cell starts 16-byte aligned (4 ids per lane per load)
+//   cmg       [R][B][mstride][Rp] uint16 cell-major copy of the groups: the
+//             row of the member in each slot of mem, so a decode pass reads
+//             every candidate's R groups sequentially beside its id
 //   hyp       [L*K][dpad]     bf16 hyperplanes (dense families)
 //   hypnorm   [L*K]           fp32 Euclidean norms of the hyperplanes
 struct Index {
@@ -64,6 +68,7 @@ struct Index {
     uint32_t nbits = 0;          // bucket width (K for SRP)
     uint32_t dpad = 0;           // dense: dim rounded up to 32
     uint32_t Rp = 1;
+    uint32_t mstride = 4;        // member slots per cell
     uint32_t cell_bytes = 2;
     uint64_t list_entries = 0;
     uint64_t device_bytes = 0;
@@ -73,6 +78,7 @@ struct Index {
     void *cells = nullptr;
     uint16_t *grp = nullptr;
     uint32_t *mem = nullptr;
+    uint16_t *cmg = nullptr;
     uint16_t *hyp = nullptr;
     float *hypnorm = nullptr;
 };

@@ -7,21 +7,22 @@
 //     reverse-index lists selected by the query's codes (Section 6: count how
 //     often each cell collides with the query);
 //   * per-repetition histograms of the nonzero counts;
-//   * a top-k key buffer.
+//   * a list of positive cells and a top-k key buffer.
 // Decode (Algorithm 3, threshold relaxation).  Walking cells by descending
 // count and reporting a point when all R of its cells have been walked means
 // a point x completes at its last-ranked cell, so the output is the k
 // smallest keys (255 - m(x), c*(x), x) with m(x) = min_r C[r, g_r(x)] and
 // c*(x) the largest cell id among x's cells of count m(x).  {x : m(x) >= t}
 // is Algorithm 2's answer at threshold t, and it lies inside the cells of
-// count >= t of any single repetition.  So a pass enumerates the members of
-// one repetition's cells with count >= t (t chosen from the histograms),
-// computes every candidate's key with one R-wide gather of its groups, and
-// keeps the smallest keys; the pass is final once at least k candidates have
-// m >= t.  When fewer than k points have m >= 1, the answer is completed
-// from repetition R-1: its positive cells hold every point whose last
-// zero-count cell lies in an earlier repetition, and the rest follow in
-// (cell, id) order from its zero-count cells.
+// count >= t of any single repetition.  So a pass streams the members of one
+// repetition's cells with count >= t (t chosen from the histograms) together
+// with each member's R group ids (stored cell-major beside the member ids, so
+// the whole pass is sequential reads), computes every key and keeps the
+// smallest; the pass is final once at least k candidates have m >= t.  When
+// fewer than k points have m >= 1, the answer is completed from repetition
+// R-1: its positive cells hold every point whose last zero-count cell lies in
+// an earlier repetition, and the rest follow in (cell, id) order from its
+// zero-count cells.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,27 +31,30 @@
 
 namespace flinng {
 
-constexpr int QT = 256;          // threads per query workgroup
-constexpr int QW = QT / 64;      // wavefronts per workgroup
+constexpr int QT = 256;            // threads per query workgroup
+constexpr int QW = QT / 64;        // wavefronts per workgroup
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
+constexpr uint32_t CL = 1024;      // positive-cell list capacity
 
 struct QArgs {
     const uint32_t *codes;
     uint64_t nq;
     const uint32_t *offsets;
     const void *cells;
-    const uint16_t *grp;
-    const uint32_t *mem;
+    const uint32_t *mem;   // [R][B][mstride] member ids
+    const uint16_t *cmg;   // [R][B][mstride][Rp] member group rows
     uint64_t N;
     uint32_t L, R, Rp, B, Bp, nbits, k, cap;
+    uint32_t mstride;      // member slots per cell (multiple of 4)
     uint32_t *ids;
     uint32_t *scores;
     uint8_t *counts_out;   // debug: write counters and skip decode
     uint32_t *work;        // persistent: next query counter (nullptr: 1 WG/query)
     uint32_t budget;
     unsigned long long *stats;  // optional per-launch totals: list entries read,
-                                // candidates enumerated (all passes), candidates
-                                // of the final pass, passes
+                                // members read (all passes), members read in
+                                // final passes, passes, group rows read in
+                                // final passes
 };
 
 struct QLayout {
@@ -69,7 +73,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_hist = o;  o += (size_t)l.hist_words * 4;
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
-    l.off_lb = o;    o += QT * 4;
+    l.off_lb = o;    o += CL * 4;
     l.off_lp = o;    o += QT * 4;
     l.off_misc = o;  o += 64 * 4;
     l.total = (o + 15) & ~(size_t)15;
@@ -77,8 +81,8 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 }
 
 // misc slots
-enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_NPOS, M_TOTAL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT,
-       M_DONE, M_THRLO, M_THRHI, M_SCAN0 };
+enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
+       M_THRHI, M_LCNT, M_MEMB, M_THI, M_SCAN0 };
 
 __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *total) {
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -121,7 +125,151 @@ __device__ inline void wg_bitonic(uint64_t *buf, uint32_t cap) {
     }
 }
 
-template <typename CellT>
+__device__ inline uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl64_up1(uint64_t v) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Per-wavefront decode state: its top-k list (lane i holds the i-th smallest
+// key), the k-th key, and tallies (uniform across the wavefront).
+struct WaveState {
+    uint64_t wl, kth;
+    uint32_t n_ge, n_all, members;
+};
+
+// Insert the keys flagged in `cand` into the wavefront's sorted top-k list.
+__device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint32_t k, int lane) {
+    unsigned long long cm = __ballot(cand && key < ws.kth);
+    while (cm) {
+        const int src = __ffsll((long long)cm) - 1;
+        cm &= cm - 1;
+        const uint64_t kk = shfl64(key, src);
+        if (kk >= ws.kth) continue;
+        const uint32_t p = (uint32_t)__popcll(__ballot(ws.wl < kk));
+        const uint64_t sh = shfl64_up1(ws.wl);
+        if ((uint32_t)lane > p) ws.wl = sh;
+        else if ((uint32_t)lane == p) ws.wl = kk;
+        if ((uint32_t)lane >= k) ws.wl = ~0ull;
+        ws.kth = shfl64(ws.wl, (int)k - 1);
+    }
+}
+
+// Load the group rows of 4 consecutive member slots (4*RP uint16, 16-byte
+// aligned for RP >= 2, 8-byte for RP = 1) as 2*RP dwords.
+template <int RP>
+__device__ inline void load_rows(const uint16_t *p, uint32_t (&w)[2 * RP]) {
+    if constexpr (RP == 1) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < RP / 2; ++i) {
+            const uint4 v = reinterpret_cast<const uint4 *>(p)[i];
+            w[4 * i + 0] = v.x;
+            w[4 * i + 1] = v.y;
+            w[4 * i + 2] = v.z;
+            w[4 * i + 3] = v.w;
+        }
+    }
+}
+
+template <int RP>
+__device__ inline uint32_t row_group(const uint32_t (&w)[2 * RP], int e, int r) {
+    const int q = e * RP + r;
+    return (w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+}
+
+// Stream the members of the cells lbs[0, nl) of one repetition: for each
+// member, its id and its group row give m and c* from the LDS counters; keys
+// with m >= level (all keys when `keep`) go into the wavefront's top-k.
+// Work items are (cell, 256-member chunk); each lane takes 4 consecutive
+// members (one 16-byte id load plus RP/2 16-byte row loads) and keeps U items
+// in flight.
+template <int RP, int U>
+__device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32_t *__restrict__ memr,
+                                  const uint16_t *__restrict__ cmgr, const uint8_t *cnt8, uint32_t R,
+                                  uint32_t Bp, uint32_t mstride, uint32_t level, bool keep,
+                                  uint32_t q0, uint32_t rem, uint32_t cpc, uint32_t k, int lane,
+                                  int wave, WaveState &ws) {
+    const uint32_t nitems = nl * cpc;
+    for (uint32_t i0 = wave; i0 < nitems; i0 += QW * U) {
+        uint4 idv[U];
+        uint32_t rows[U][2 * RP];
+        uint32_t nv[U];
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            const uint32_t i = i0 + (uint32_t)g * QW;
+            nv[g] = 0;
+            idv[g] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int w = 0; w < 2 * RP; ++w) rows[g][w] = 0;
+            if (i < nitems) {
+                const uint32_t bb = lbs[i / cpc];
+                const uint32_t j = (i % cpc) * 256 + 4 * lane;
+                const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
+                if (j < sz) {
+                    nv[g] = (sz - j < 4) ? sz - j : 4u;
+                    const uint64_t slot = (uint64_t)bb * mstride + j;
+                    idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
+                    load_rows<RP>(cmgr + slot * RP, rows[g]);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            uint32_t c = nv[g];
+            for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+            ws.members += c;
+            const uint32_t xs[4] = {idv[g].x, idv[g].y, idv[g].z, idv[g].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool val = (uint32_t)e < nv[g];
+                uint32_t m = 0xFFFFFFFFu, cs = 0;
+#pragma unroll
+                for (int r = 0; r < RP; ++r) {
+                    if ((uint32_t)r < R) {
+                        const uint32_t cc = r * Bp + row_group<RP>(rows[g], e, r);
+                        const uint32_t v = cnt8[cc];
+                        if (v <= m) {  // later repetitions have larger cell ids
+                            m = v;
+                            cs = cc;
+                        }
+                    }
+                }
+                const bool ge = val && m >= level;
+                const bool take = val && (keep || ge);
+                ws.n_ge += (uint32_t)__popcll(__ballot(ge));
+                ws.n_all += (uint32_t)__popcll(__ballot(take));
+                const uint64_t key = ((uint64_t)(255u - (m & 255u)) << 56) | ((uint64_t)cs << 32) | xs[e];
+                wave_insert(ws, key, take, k, lane);
+            }
+        }
+    }
+}
+
+// m and c* of one member from its group row (general-k path).
+__device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t Bp, const uint8_t *cnt8,
+                                     uint32_t &m, uint32_t &cs) {
+    m = 0xFFFFFFFFu;
+    cs = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t c = r * Bp + row[r];
+        const uint32_t v = cnt8[c];
+        if (v <= m) {
+            m = v;
+            cs = c;
+        }
+    }
+}
+
+template <typename CellT, int RP>
 __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
     extern __shared__ __align__(16) unsigned char lds[];
     const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap);
@@ -141,6 +289,8 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
     const uint64_t nbk1 = (1ull << A.nbits) + 1;
     const uint32_t q0 = (uint32_t)(A.N / B), rem = (uint32_t)(A.N % B);
     const uint32_t gmax = q0 + (rem ? 1u : 0u);
+    const uint32_t cpc = (gmax + 255) / 256;  // 256-member chunks per cell
+    const uint64_t rstride = (uint64_t)B * A.mstride;
     const CellT *cells = static_cast<const CellT *>(A.cells);
 
     uint64_t q = blockIdx.x;
@@ -192,7 +342,6 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             for (uint32_t c = tid; c < R * B; c += QT) out[c] = cnt8[(c / B) * Bp + c % B];
             __syncthreads();
             if (!A.work) break;
-            q = A.nq;  // unreachable in persistent mode: loop continues via counter
             continue;
         }
 
@@ -211,46 +360,82 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             }
         }
         __syncthreads();
-        // fold per-wave copies into copy 0, then suffix sums per repetition
         for (uint32_t i = tid; i < R * (L + 1); i += QT) {
-            uint32_t s = 0;
+            uint32_t sacc = 0;
 #pragma unroll
-            for (int w = 0; w < QW; ++w) s += hist[w * R * (L + 1) + i];
-            hist[i] = s;
+            for (int w = 0; w < QW; ++w) sacc += hist[w * R * (L + 1) + i];
+            hist[i] = sacc;
         }
         __syncthreads();
-        for (uint32_t r = tid; r < R; r += QT) {
-            uint32_t run = 0;
-            for (int v = (int)L; v >= 1; --v) {
-                run += hist[r * (L + 1) + v];
-                hist[r * (L + 1) + v] = run;  // cells with count >= v
+        // suffix sums per repetition (one wavefront per repetition, 4 levels
+        // per lane): hist[r][v] = cells of repetition r with count >= v
+        for (uint32_t r = wave; r < R; r += QW) {
+            uint32_t *h = hist + r * (L + 1);
+            uint32_t v[4], loc = 0;
+#pragma unroll
+            for (int j = 3; j >= 0; --j) {
+                const uint32_t idx = 4 * lane + j;
+                v[j] = (idx <= L && idx >= 1) ? h[idx] : 0u;
+                loc += v[j];
+                v[j] = loc;  // suffix within the lane's 4 levels
             }
-            hist[r * (L + 1)] = B;
+            uint32_t above = loc;  // inclusive suffix over lanes >= lane
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_down((int)above, o, 64);
+                if (lane + o < 64) above += y;
+            }
+            const uint32_t after = above - loc;  // lanes > lane
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t idx = 4 * lane + j;
+                if (idx <= L && idx >= 1) h[idx] = v[j] + after;
+            }
+            if (lane == 0) h[0] = B;
         }
         __syncthreads();
-        // S_r[t] upper bound = cells_r(>= t) * ceil(N/B); minS[t] over r.
-        // Choose the first level: t_hi = max t >= 1 with minS[t] >= k; then the
-        // lowest level <= t_hi whose enumeration stays within the budget.
+        // ms[t] = min over repetitions of cells with count >= t (the list
+        // offsets are no longer needed, so `pre` holds it).  Enumerating the
+        // level-t cells of the cheapest repetition reads about ms[t]*ceil(N/B)
+        // members; ms is non-increasing in t.
+        uint32_t *ms = pre;
+        for (uint32_t t = tid; t <= L; t += QT) {
+            uint32_t mn = 0xFFFFFFFFu;
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint32_t c = hist[r * (L + 1) + t];
+                mn = c < mn ? c : mn;
+            }
+            ms[t] = mn;
+        }
         if (tid == 0) {
-            auto minS = [&](uint32_t t) -> uint64_t {
-                uint64_t m = ~0ull;
-                for (uint32_t r = 0; r < R; ++r) {
-                    uint64_t s = (uint64_t)hist[r * (L + 1) + t] * gmax;
-                    m = s < m ? s : m;
-                }
-                return m;
-            };
-            uint32_t thi = 0;
-            for (uint32_t t = L; t >= 1; --t)
-                if (minS(t) >= k) { thi = t; break; }
-            uint32_t level = 0;
-            if (thi >= 1) {
-                level = thi;
-                for (uint32_t t = 1; t <= thi; ++t)
-                    if (minS(t) <= A.budget) { level = t; break; }
-            }
-            misc[M_LEVEL] = level;
+            misc[M_NEXT] = 0;
             misc[M_DONE] = 0;
+            misc[M_THI] = 0;
+        }
+        __syncthreads();
+        // t_hi = #{t in 1..L : ms[t]*gmax >= k} (a prefix of levels);
+        // t_lo = #{t in 1..L : ms[t]*gmax <= budget} (a suffix of levels).
+        {
+            uint32_t c_hi = 0, c_lo = 0;
+            for (uint32_t t = 1 + tid; t <= L; t += QT) {
+                const uint64_t sz = (uint64_t)ms[t] * gmax;
+                c_hi += (sz >= k) ? 1u : 0u;
+                c_lo += (sz <= A.budget) ? 1u : 0u;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                c_hi += (uint32_t)__shfl_xor((int)c_hi, o, 64);
+                c_lo += (uint32_t)__shfl_xor((int)c_lo, o, 64);
+            }
+            if (lane == 0) {
+                atomicAdd(&misc[M_THI], c_hi);
+                atomicAdd(&misc[M_NEXT], c_lo);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const uint32_t thi = misc[M_THI];
+            const uint32_t tlo = L + 1 - misc[M_NEXT];  // lowest level within the budget
+            misc[M_LEVEL] = (thi == 0) ? 0u : (tlo <= thi ? tlo : thi);
         }
         __syncthreads();
 
@@ -265,12 +450,15 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                     rep = R - 1;
                     keep = 1;
                 } else {
-                    uint64_t best = ~0ull;
+                    uint32_t best = 0xFFFFFFFFu;
                     rep = 0;
                     for (uint32_t r = 0; r < R; ++r) {
-                        uint64_t s = hist[r * (L + 1) + level];
-                        if (s < best) { best = s; rep = r; }
+                        const uint32_t sc = hist[r * (L + 1) + level];
+                        if (sc < best) { best = sc; rep = r; }
                     }
+                    // level 1: one pass over repetition R-1 keeping every key
+                    // serves both outcomes (m >= 1 for k points, or the
+                    // zero-count completion) when it is not much larger
                     if (level == 1 &&
                         (uint64_t)hist[(R - 1) * (L + 1) + 1] * gmax <= 2ull * A.budget) {
                         rep = R - 1;
@@ -285,14 +473,91 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 misc[M_NALL] = 0;
                 misc[M_THRLO] = 0xFFFFFFFFu;
                 misc[M_THRHI] = 0xFFFFFFFFu;
+                misc[M_LCNT] = 0;
+                misc[M_MEMB] = 0;
             }
             __syncthreads();
             const uint32_t level = misc[M_LEVEL], rep = misc[M_REP];
             const bool keep = misc[M_KEEPALL] != 0;
-            const uint32_t *memr = A.mem + (uint64_t)rep * A.N;
-            uint32_t n_ge = 0, n_all = 0;  // per-thread tallies (lane 0 of each wave)
-            unsigned long long pass_members = 0;
+            const uint32_t *memr = A.mem + rep * rstride;
+            const uint16_t *cmgr = A.cmg + rep * rstride * RP;
 
+          if (k <= 64) {
+            // Fast decode (k <= 64): the positive cells of `rep` go into an
+            // LDS list (one word-wide scan, or 256 cells at a time when they
+            // do not fit); each wavefront streams (cell, 256-member chunk)
+            // items with several in flight per lane and keeps its own top-k
+            // in registers; the lists are merged by rank at the end.
+            WaveState ws{~0ull, ~0ull, 0u, 0u, 0u};
+            const uint32_t nrep = hist[rep * (L + 1) + level];
+            if (nrep <= CL) {
+                for (uint32_t w = tid; w < Bp / 4; w += QT) {
+                    const uint32_t v = cnt32[rep * (Bp / 4) + w];
+                    if (!v) continue;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t b = 4 * w + j;
+                        if (b < B && ((v >> (8 * j)) & 255u) >= level)
+                            lb[atomicAdd(&misc[M_LCNT], 1u)] = b;
+                    }
+                }
+                __syncthreads();
+                walk_cells<RP, (RP >= 8 ? 1 : 2)>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride,
+                                                  level, keep, q0, rem, cpc, k, lane, wave, ws);
+            } else {
+                const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+                for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
+                    const uint32_t b = cb0 + tid;
+                    const bool pos = (b < B) && (cnt8[rep * Bp + b] >= level);
+                    const unsigned long long pm = __ballot(pos);
+                    uint32_t wbase = 0;
+                    if (lane == 0 && pm) wbase = atomicAdd(&misc[M_LCNT], (uint32_t)__popcll(pm));
+                    wbase = (uint32_t)__shfl((int)wbase, 0, 64);
+                    if (pos) lb[wbase + (uint32_t)__popcll(pm & ltmask)] = b;
+                    __syncthreads();
+                    const uint32_t nl = misc[M_LCNT];
+                    if (nl > CL - QT || cb0 + QT >= B) {
+                        walk_cells<RP, (RP >= 8 ? 1 : 2)>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride,
+                                                          level, keep, q0, rem, cpc, k, lane, wave, ws);
+                        __syncthreads();
+                        if (tid == 0) misc[M_LCNT] = 0;
+                        __syncthreads();
+                    }
+                }
+            }
+            // merge the per-wave lists: rank of each key among all lists
+            uint64_t *wlist = buf + 256;
+            wlist[wave * 64 + lane] = ws.wl;
+            if (lane == 0) {
+                atomicAdd(&misc[M_NGE], ws.n_ge);
+                atomicAdd(&misc[M_NALL], ws.n_all);
+                atomicAdd(&misc[M_MEMB], ws.members);
+            }
+            __syncthreads();
+            if ((uint32_t)tid < QW * k) {
+                const uint32_t w = tid / k, i = tid % k;
+                const uint64_t key = wlist[w * 64 + i];
+                if (key != ~0ull) {
+                    uint32_t rank = i;
+                    for (uint32_t w2 = 0; w2 < (uint32_t)QW; ++w2) {
+                        if (w2 == w) continue;
+                        uint32_t lo = 0, hi = k;  // keys of list w2 below `key`
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (wlist[w2 * 64 + mid] < key) lo = mid + 1; else hi = mid;
+                        }
+                        rank += lo;
+                    }
+                    if (rank < k) buf[rank] = key;
+                }
+            }
+            __syncthreads();
+          } else {
+            // General k: cells 256 at a time, candidates appended to a
+            // capacity-cap LDS buffer under a tightening threshold; the
+            // buffer is sorted and cut to k when nearly full.
+            uint32_t n_ge = 0, n_all = 0;  // per-wave tallies (lane 0 of each wave)
+            unsigned long long pass_members = 0;
             for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
                 const uint32_t b = cb0 + tid;
                 uint32_t cval = 0;
@@ -319,26 +584,18 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                             uint32_t mid = (lo + hi) >> 1;
                             if (lp[mid] <= idx) lo = mid; else hi = mid;
                         }
-                        const uint32_t bb = lb[lo];
-                        const uint32_t x = memr[(uint64_t)bb * q0 + (bb < rem ? bb : rem) + (idx - lp[lo])];
-                        const uint16_t *gx = A.grp + (uint64_t)x * A.Rp;
-                        uint32_t m = 0xFFFFFFFFu, cs = 0;
-                        for (uint32_t r = 0; r < R; ++r) {
-                            const uint32_t c = r * Bp + gx[r];
-                            const uint32_t v = cnt8[c];
-                            if (v <= m) {  // later repetitions have larger cell ids
-                                m = v;
-                                cs = c;
-                            }
-                        }
+                        const uint64_t slot = (uint64_t)lb[lo] * A.mstride + (idx - lp[lo]);
+                        const uint32_t x = memr[slot];
+                        uint32_t m, cs;
+                        slot_min_cell(cmgr + slot * RP, R, Bp, cnt8, m, cs);
                         ge = m >= level;
                         take = keep || ge;
                         key = ((uint64_t)(255u - m) << 56) | ((uint64_t)cs << 32) | x;
                         if (take) {
                             const uint64_t thr = ((uint64_t)misc[M_THRHI] << 32) | misc[M_THRLO];
                             if (key < thr) {
-                                const uint32_t slot = atomicAdd(&misc[M_BUFN], 1u);
-                                buf[slot] = key;
+                                const uint32_t slotb = atomicAdd(&misc[M_BUFN], 1u);
+                                buf[slotb] = key;
                             }
                         }
                     }
@@ -368,11 +625,11 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 }
                 __syncthreads();
             }
-            // pass totals
             if (lane == 0) {
                 atomicAdd(&misc[M_NGE], n_ge);
                 atomicAdd(&misc[M_NALL], n_all);
             }
+            if (tid == 0) atomicAdd(&misc[M_MEMB], (uint32_t)pass_members);
             __syncthreads();
             {
                 const uint32_t nb = misc[M_BUFN];
@@ -380,11 +637,12 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             }
             __syncthreads();
             wg_bitonic(buf, cap);
+          }
             const uint32_t nge = misc[M_NGE], nall = misc[M_NALL];
             const bool ok = nge >= k;
-            st_all += pass_members;
+            st_all += misc[M_MEMB];
             st_passes += 1;
-            if (ok || keep) st_final = pass_members;
+            if (ok || keep) st_final = misc[M_MEMB];
             if (ok || keep) {
                 // emit the buffered keys (and, for the fill path, zero cells)
                 const uint32_t nres = (nall < k ? nall : k);
@@ -398,7 +656,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 if (!ok && nres < k && wave == 0) {
                     // zero fill from repetition R-1, cells ascending, ids ascending
                     uint32_t need = k - nres, outp = nres;
-                    const uint32_t *memz = A.mem + (uint64_t)(R - 1) * A.N;
+                    const uint32_t *memz = A.mem + (R - 1) * rstride;
                     for (uint32_t b0 = 0; b0 < B && need; b0 += 64) {
                         const uint32_t b = b0 + lane;
                         const bool z = (b < B) && (cnt8[(R - 1) * Bp + b] == 0);
@@ -408,7 +666,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                             zm &= zm - 1;
                             const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
                             const uint32_t takeN = sz < need ? sz : need;
-                            const uint64_t mo = (uint64_t)bb * q0 + (bb < rem ? bb : rem);
+                            const uint64_t mo = (uint64_t)bb * A.mstride;
                             for (uint32_t j = lane; j < takeN; j += 64) {
                                 oid[outp + j] = memz[mo + j];
                                 if (osc) osc[outp + j] = 0u;
@@ -423,21 +681,23 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                     }
                 }
                 if (tid == 0) misc[M_DONE] = 1;
-            } else if (tid == 0) {
-                // lower the level: the lowest level whose minimum enumeration
+            } else {
+                // lower the level: the lowest level whose cheapest enumeration
                 // stays within 8x the larger of the budget and this pass
                 const uint32_t lv = misc[M_LEVEL];
-                uint64_t lim = 8ull * (A.budget > nall ? A.budget : nall);
-                uint32_t next = lv - 1;
-                for (uint32_t t = 1; t < lv; ++t) {
-                    uint64_t m = ~0ull;
-                    for (uint32_t r = 0; r < R; ++r) {
-                        uint64_t s = (uint64_t)hist[r * (L + 1) + t] * gmax;
-                        m = s < m ? s : m;
-                    }
-                    if (m <= lim) { next = t; break; }
+                const uint64_t lim = 8ull * (A.budget > nall ? A.budget : nall);
+                __syncthreads();
+                if (tid == 0) misc[M_NEXT] = 0;
+                __syncthreads();
+                uint32_t c = 0;
+                for (uint32_t t = 1 + tid; t <= L; t += QT) c += ((uint64_t)ms[t] * gmax <= lim) ? 1u : 0u;
+                for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+                if (lane == 0) atomicAdd(&misc[M_NEXT], c);
+                __syncthreads();
+                if (tid == 0) {
+                    const uint32_t t1 = L + 1 - misc[M_NEXT];
+                    misc[M_LEVEL] = (t1 < lv) ? t1 : lv - 1;  // 0 selects the fill path
                 }
-                misc[M_LEVEL] = next;  // 0 selects the fill path
             }
             __syncthreads();
             if (misc[M_DONE]) break;
@@ -447,6 +707,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             atomicAdd(&A.stats[1], st_all);
             atomicAdd(&A.stats[2], st_final);
             atomicAdd(&A.stats[3], st_passes);
+            atomicAdd(&A.stats[4], st_final);
         }
         __syncthreads();
         if (!A.work) break;
@@ -464,7 +725,7 @@ static uint32_t cap_for(uint32_t k) {
 }
 
 size_t query_lds_bytes(const Index &ix, uint32_t k) {
-    uint32_t Bp = (ix.p.B + 3) & ~3u;
+    const uint32_t Bp = (ix.p.B + 3) & ~3u;
     return q_layout(ix.p.L, ix.p.R, Bp, cap_for(k)).total;
 }
 
@@ -494,23 +755,35 @@ static int num_cus() {
     return v;
 }
 
-template <typename CellT>
-static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
+template <typename CellT, int RP>
+static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
         attr_set = true;
     }
     uint64_t grid = a.nq;
     if (persistent) {
-        const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)(160 * 1024) / std::max<size_t>(lds, 1)));
+        const uint64_t per_cu = std::max<uint64_t>(
+            1, std::min<uint64_t>(8, (uint64_t)(160 * 1024) / std::max<size_t>(lds, 1)));
         grid = std::min<uint64_t>(a.nq, per_cu * (uint64_t)num_cus());
     }
     if (grid == 0) return;
     if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
-    hipLaunchKernelGGL(query_kernel<CellT>, dim3((unsigned)grid), dim3(QT), lds, s, a);
+    hipLaunchKernelGGL((query_kernel<CellT, RP>), dim3((unsigned)grid), dim3(QT), lds, s, a);
     FL_CHECK_LAUNCH();
+}
+
+template <typename CellT>
+static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
+    switch (a.Rp) {
+        case 1: launch_rp<CellT, 1>(a, lds, persistent, s); break;
+        case 2: launch_rp<CellT, 2>(a, lds, persistent, s); break;
+        case 4: launch_rp<CellT, 4>(a, lds, persistent, s); break;
+        case 8: launch_rp<CellT, 8>(a, lds, persistent, s); break;
+        default: launch_rp<CellT, 16>(a, lds, persistent, s); break;
+    }
 }
 
 static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint32_t k) {
@@ -519,8 +792,8 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.nq = nq;
     a.offsets = ix.offsets;
     a.cells = ix.cells;
-    a.grp = ix.grp;
     a.mem = ix.mem;
+    a.cmg = ix.cmg;
     a.N = ix.N;
     a.L = ix.p.L;
     a.R = ix.p.R;
@@ -530,6 +803,7 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.nbits = ix.nbits;
     a.k = k;
     a.cap = cap_for(k);
+    a.mstride = ix.mstride;
     a.budget = BUDGET;
     return a;
 }

@@ -84,7 +84,7 @@ def test_minhash_codes_random(fl, family, K, L, b, mean):
 # --------------------------------------------------------------------------
 # whole pipeline on the workloads (scaled where the oracle needs it)
 
-def _check_all(fl, family, data, q, K, L, R, B, seed, bucket_bits, ks=(1, 10, 37)):
+def _check_all(fl, family, data, q, K, L, R, B, seed, bucket_bits, ks=(1, 10, 37, 64, 65, 200)):
     gi, oi = build_both(fl, family, data, K, L, R, B, seed, bucket_bits)
     log("built", family, "N", oi.N, "entries", gi.info.list_entries)
     # index
@@ -175,3 +175,40 @@ def test_errors(fl):
         gi.query(X[:3], 0)
     with pytest.raises(fl.FlinngError):
         gi.query(X[:3], 5000)
+
+
+def test_c4_grid_u32_cells_large_lds(fl):
+    """R*B = 131072 cells: 32-bit cell ids and 128 KiB of LDS counters per
+    workgroup, the URL workload's grid, on a small dataset."""
+    X, Q, _ = synth.dense_gmm(N=40000, d=16, n_centres=400, sigma=0.05, nq=80)
+    gi, oi = build_both(fl, 0, X, 6, 5, 8, 16384, 21, 0)
+    assert gi.info.cell_id_bytes == 4
+    offs, cells, groups = gi.export()
+    assert np.array_equal(groups, oi.g) and np.array_equal(cells, oi.cells)
+    assert np.array_equal(gi.debug_counts(Q), oi.counts(oi.hash(Q)))
+    for k in (1, 10, 64, 65):
+        want = oracle_query(oi, Q, k)
+        for pers in (False, True):
+            got = gi.query(Q, k, persistent=pers)
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (k, pers)
+
+
+def test_c2_genome_hashed_filter(fl):
+    """N = 40 000 > 2^15: the decode's membership bitmaps are hashed (false
+    positives possible, resolved by the exact group gather)."""
+    cfg, (it, of), (qit, qof), _ = scaled("c2", 0.04, 100)
+    _check_all(fl, 3, (it, of), (qit, qof), cfg["K"], cfg["L"], cfg["R"], cfg["B"], 9,
+               cfg["bucket_bits"], ks=(1, 10, 64))
+
+
+@pytest.mark.parametrize("R", [2, 5])
+def test_many_positive_cells_chunked(fl, R):
+    """One 1-bit table: about half of all cells are positive, more than the
+    decode's single-scan cell list holds, so cells are streamed 256 at a
+    time (with and without membership bitmaps)."""
+    X, Q, _ = synth.dense_gmm(N=20000, d=8, n_centres=50, nq=40)
+    gi, oi = build_both(fl, 0, X, 1, 1, R, 2000, 23, 0)
+    for k in (1, 10, 64):
+        want = oracle_query(oi, Q, k)
+        got = gi.query(Q, k)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), k

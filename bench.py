@@ -181,7 +181,7 @@ def main():
         "metric": "queries/s at recall@10>=0.9, served vs plain batched; p50/p99 query latency",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if dense else "u64",
+        "scaling": "weak", "vs_baseline": None, "dtype": ("bf16+f32acc+f64" if fam == fl.SRP_BF16 else "f32+f64") if dense else "u64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "N": cfg["N"], "nq": nq, "K": K, "L": L, "R": R,
                    "B": B, "bucket_bits": b, "k": k, "persistent": bool(args.persistent)},
@@ -195,12 +195,8 @@ def main():
         t = time.time()
         ns = min(args.recall_queries, nq)
         if dense:
-            X = data if fam == fl.SRP_F32 else None
-            from workloads.synth import bf16_to_f32
-            Xf = data if fam == fl.SRP_F32 else bf16_to_f32(data)
-            Qf = queries if fam == fl.SRP_F32 else bf16_to_f32(queries)
-            ti, _ = truth.cosine_topk(Xf, Qf[:ns], 10)
-            del X
+            ti, _ = truth.cosine_topk_gpu(data, queries[:ns], 10,
+                                          dense_bf16=(fam == fl.SRP_BF16))
         else:
             ji = truth.JaccardIndex(data[0], data[1])
             ti, _ = ji.topk(queries[0], queries[1][:ns + 1], 10)
@@ -210,13 +206,16 @@ def main():
 
     # ---- served: continuous batching of uneven requests (sizes 1..512)
     if not args.no_serve:
-        rng = np.random.default_rng(4)
-        sizes = []
-        tot = 0
-        while tot < nq:
-            s_ = int(min(rng.integers(1, 513), nq - tot))
-            sizes.append(s_)
-            tot += s_
+        if "group_sizes" in cfg:
+            sizes = [int(v) for v in cfg["group_sizes"]]   # the workload's uneven groups
+        else:
+            rng = np.random.default_rng(4)
+            sizes = []
+            tot = 0
+            while tot < nq:
+                s_ = int(min(rng.integers(1, 513), nq - tot))
+                sizes.append(s_)
+                tot += s_
         srv = fl.Server([gi], mem_budget=8 << 30, max_inflight=4, max_batch=4096,
                         persistent=args.persistent)
         reqs = []

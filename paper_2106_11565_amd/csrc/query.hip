@@ -31,8 +31,13 @@
 
 namespace flinng {
 
-constexpr int QT = 256;            // threads per query workgroup
-constexpr int QW = QT / 64;        // wavefronts per workgroup
+// Threads per query workgroup: 256, or 1024 when the per-query LDS state
+// leaves room for only one workgroup per CU (more wavefronts to hide
+// latency).  Histogram copies: one per wavefront up to HCMAX.
+constexpr int HCMAX = 4;
+__host__ __device__ constexpr int hist_copies(int T) {
+    return (T / 64) < HCMAX ? (T / 64) : (T >= 1024 ? 2 : HCMAX);
+}
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
 constexpr uint32_t CL = 1024;      // positive-cell list capacity
 
@@ -46,6 +51,7 @@ struct QArgs {
     uint64_t N;
     uint32_t L, R, Rp, B, Bp, nbits, k, cap;
     uint32_t mstride;      // member slots per cell (multiple of 4)
+    uint32_t threads;      // workgroup size the kernel is launched with
     uint32_t *ids;
     uint32_t *scores;
     uint8_t *counts_out;   // debug: write counters and skip decode
@@ -62,10 +68,11 @@ struct QLayout {
     size_t off_cnt, off_hist, off_pre, off_start, off_buf, off_lb, off_lp, off_misc, total;
 };
 
-__host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp, uint32_t cap) {
+__host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp, uint32_t cap,
+                                            int T) {
     QLayout l;
     l.cnt_words = (R * Bp) / 4;
-    l.hist_words = QW * R * (L + 1);
+    l.hist_words = hist_copies(T) * R * (L + 1);
     l.cap = cap;
     size_t o = 0;
     l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned first
@@ -74,7 +81,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
     l.off_lb = o;    o += CL * 4;
-    l.off_lp = o;    o += QT * 4;
+    l.off_lp = o;    o += (size_t)T * 4;
     l.off_misc = o;  o += 64 * 4;
     l.total = (o + 15) & ~(size_t)15;
     return l;
@@ -84,7 +91,9 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
        M_THRHI, M_LCNT, M_MEMB, M_THI, M_SCAN0 };
 
+template <int T>
 __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *total) {
+    constexpr int TW = T / 64;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     uint32_t inc = v;
 #pragma unroll
@@ -96,7 +105,7 @@ __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *tot
     __syncthreads();
     uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < QW; ++w) {
+    for (int w = 0; w < TW; ++w) {
         uint32_t c = scr[w];
         pre += (w < wave) ? c : 0u;
         tot += c;
@@ -107,10 +116,11 @@ __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *tot
 }
 
 // Bitonic sort of buf[0, cap) ascending (cap a power of two).
+template <int T>
 __device__ inline void wg_bitonic(uint64_t *buf, uint32_t cap) {
     for (uint32_t size = 2; size <= cap; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = threadIdx.x; i < cap / 2; i += QT) {
+            for (uint32_t i = threadIdx.x; i < cap / 2; i += T) {
                 uint32_t lo = 2 * i - (i & (stride - 1));
                 uint32_t hi = lo + stride;
                 bool up = ((lo & size) == 0);
@@ -192,20 +202,21 @@ __device__ inline uint32_t row_group(const uint32_t (&w)[2 * RP], int e, int r) 
 // Work items are (cell, 256-member chunk); each lane takes 4 consecutive
 // members (one 16-byte id load plus RP/2 16-byte row loads) and keeps U items
 // in flight.
-template <int RP, int U>
+template <int RP, int U, int T>
 __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32_t *__restrict__ memr,
                                   const uint16_t *__restrict__ cmgr, const uint8_t *cnt8, uint32_t R,
                                   uint32_t Bp, uint32_t mstride, uint32_t level, bool keep,
                                   uint32_t q0, uint32_t rem, uint32_t cpc, uint32_t k, int lane,
                                   int wave, WaveState &ws) {
+    constexpr int TW = T / 64;
     const uint32_t nitems = nl * cpc;
-    for (uint32_t i0 = wave; i0 < nitems; i0 += QW * U) {
+    for (uint32_t i0 = wave; i0 < nitems; i0 += TW * U) {
         uint4 idv[U];
         uint32_t rows[U][2 * RP];
         uint32_t nv[U];
 #pragma unroll
         for (int g = 0; g < U; ++g) {
-            const uint32_t i = i0 + (uint32_t)g * QW;
+            const uint32_t i = i0 + (uint32_t)g * TW;
             nv[g] = 0;
             idv[g] = make_uint4(0, 0, 0, 0);
 #pragma unroll
@@ -269,10 +280,12 @@ __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t B
     }
 }
 
-template <typename CellT, int RP>
+template <typename CellT, int RP, int QT>
 __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
+    constexpr int QW = QT / 64;
+    constexpr int HC = hist_copies(QT);
     extern __shared__ __align__(16) unsigned char lds[];
-    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap);
+    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap, QT);
     uint64_t *buf = reinterpret_cast<uint64_t *>(lds + lay.off_buf);
     uint32_t *cnt32 = reinterpret_cast<uint32_t *>(lds + lay.off_cnt);
     const uint8_t *cnt8 = lds + lay.off_cnt;
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             len = o[1] - st;
         }
         uint32_t total;
-        uint32_t ex = wg_excl_scan(len, scr, &total);
+        uint32_t ex = wg_excl_scan<QT>(len, scr, &total);
         if ((uint32_t)tid < L) {
             pre[tid] = ex;
             lstart[tid] = st;
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
 
         // ---- 4. per-repetition histograms of nonzero counts (per-wave copies)
         {
-            uint32_t *hw = hist + wave * R * (L + 1);
+            uint32_t *hw = hist + (wave % HC) * R * (L + 1);
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
                 uint32_t v = cnt32[w];
                 if (!v) continue;
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         for (uint32_t i = tid; i < R * (L + 1); i += QT) {
             uint32_t sacc = 0;
 #pragma unroll
-            for (int w = 0; w < QW; ++w) sacc += hist[w * R * (L + 1) + i];
+            for (int w = 0; w < HC; ++w) sacc += hist[w * R * (L + 1) + i];
             hist[i] = sacc;
         }
         __syncthreads();
@@ -502,7 +515,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                     }
                 }
                 __syncthreads();
-                walk_cells<RP, (RP >= 8 ? 1 : 2)>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride,
+                walk_cells<RP, (RP >= 8 ? 1 : 2), QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride,
                                                   level, keep, q0, rem, cpc, k, lane, wave, ws);
             } else {
                 const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -517,7 +530,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                     __syncthreads();
                     const uint32_t nl = misc[M_LCNT];
                     if (nl > CL - QT || cb0 + QT >= B) {
-                        walk_cells<RP, (RP >= 8 ? 1 : 2)>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride,
+                        walk_cells<RP, (RP >= 8 ? 1 : 2), QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride,
                                                           level, keep, q0, rem, cpc, k, lane, wave, ws);
                         __syncthreads();
                         if (tid == 0) misc[M_LCNT] = 0;
@@ -526,7 +539,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 }
             }
             // merge the per-wave lists: rank of each key among all lists
-            uint64_t *wlist = buf + 256;
+            uint64_t *wlist = buf + 64;
             wlist[wave * 64 + lane] = ws.wl;
             if (lane == 0) {
                 atomicAdd(&misc[M_NGE], ws.n_ge);
@@ -565,8 +578,8 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 const bool pos = (b < B) && (cval >= level);
                 const uint32_t sz = pos ? (q0 + (b < rem ? 1u : 0u)) : 0u;
                 uint32_t npos, tsz;
-                const uint32_t ci = wg_excl_scan(pos ? 1u : 0u, scr, &npos);
-                const uint32_t ps = wg_excl_scan(sz, scr, &tsz);
+                const uint32_t ci = wg_excl_scan<QT>(pos ? 1u : 0u, scr, &npos);
+                const uint32_t ps = wg_excl_scan<QT>(sz, scr, &tsz);
                 if (pos) {
                     lb[ci] = b;
                     lp[ci] = ps;
@@ -611,7 +624,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                         const uint32_t nb = misc[M_BUFN];
                         for (uint32_t i = nb + tid; i < cap; i += QT) buf[i] = ~0ull;
                         __syncthreads();
-                        wg_bitonic(buf, cap);
+                        wg_bitonic<QT>(buf, cap);
                         if (tid == 0) {
                             const uint32_t keepn = nb < k ? nb : k;
                             misc[M_BUFN] = keepn;
@@ -636,7 +649,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 for (uint32_t i = nb + tid; i < cap; i += QT) buf[i] = ~0ull;
             }
             __syncthreads();
-            wg_bitonic(buf, cap);
+            wg_bitonic<QT>(buf, cap);
           }
             const uint32_t nge = misc[M_NGE], nall = misc[M_NALL];
             const bool ok = nge >= k;
@@ -717,16 +730,30 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
 // ---------------------------------------------------------------------------
 uint32_t query_max_k() { return 4096; }
 
-static uint32_t cap_for(uint32_t k) {
-    uint32_t need = std::max<uint32_t>(512u, k + QT);
+// Top-k buffer capacity: room for k kept keys plus one round of T appends
+// (general path), and for the fast path's per-wave lists at buf[64..).
+static uint32_t cap_for(uint32_t k, int T) {
+    uint32_t need = std::max<uint32_t>(std::max<uint32_t>(512u, k + (uint32_t)T), 64u + (uint32_t)T);
     uint32_t c = 1;
     while (c < need) c <<= 1;
     return c;
 }
 
+static int max_lds();
+
+// 1024 threads when a 256-thread workgroup's state already fills more than
+// half of the LDS (one workgroup per CU either way), else 256.
+static int threads_for(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
+    const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256).total;
+    if (small * 2 <= (size_t)max_lds()) return 256;
+    const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024).total;
+    return big <= (size_t)max_lds() ? 1024 : 256;
+}
+
 size_t query_lds_bytes(const Index &ix, uint32_t k) {
     const uint32_t Bp = (ix.p.B + 3) & ~3u;
-    return q_layout(ix.p.L, ix.p.R, Bp, cap_for(k)).total;
+    const int T = threads_for(ix.p.L, ix.p.R, Bp, k);
+    return q_layout(ix.p.L, ix.p.R, Bp, cap_for(k, T), T).total;
 }
 
 static int max_lds() {
@@ -755,11 +782,11 @@ static int num_cus() {
     return v;
 }
 
-template <typename CellT, int RP>
+template <typename CellT, int RP, int QT>
 static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
         attr_set = true;
     }
@@ -771,19 +798,27 @@ static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s
     }
     if (grid == 0) return;
     if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
-    hipLaunchKernelGGL((query_kernel<CellT, RP>), dim3((unsigned)grid), dim3(QT), lds, s, a);
+    hipLaunchKernelGGL((query_kernel<CellT, RP, QT>), dim3((unsigned)grid), dim3(QT), lds, s, a);
     FL_CHECK_LAUNCH();
+}
+
+template <typename CellT, int QT>
+static void launch_t(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
+    switch (a.Rp) {
+        case 1: launch_rp<CellT, 1, QT>(a, lds, persistent, s); break;
+        case 2: launch_rp<CellT, 2, QT>(a, lds, persistent, s); break;
+        case 4: launch_rp<CellT, 4, QT>(a, lds, persistent, s); break;
+        case 8: launch_rp<CellT, 8, QT>(a, lds, persistent, s); break;
+        default: launch_rp<CellT, 16, QT>(a, lds, persistent, s); break;
+    }
 }
 
 template <typename CellT>
 static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
-    switch (a.Rp) {
-        case 1: launch_rp<CellT, 1>(a, lds, persistent, s); break;
-        case 2: launch_rp<CellT, 2>(a, lds, persistent, s); break;
-        case 4: launch_rp<CellT, 4>(a, lds, persistent, s); break;
-        case 8: launch_rp<CellT, 8>(a, lds, persistent, s); break;
-        default: launch_rp<CellT, 16>(a, lds, persistent, s); break;
-    }
+    if (a.threads == 1024)
+        launch_t<CellT, 1024>(a, lds, persistent, s);
+    else
+        launch_t<CellT, 256>(a, lds, persistent, s);
 }
 
 static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint32_t k) {
@@ -802,7 +837,8 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.Bp = (ix.p.B + 3) & ~3u;
     a.nbits = ix.nbits;
     a.k = k;
-    a.cap = cap_for(k);
+    a.threads = threads_for(a.L, a.R, a.Bp, k);
+    a.cap = cap_for(k, (int)a.threads);
     a.mstride = ix.mstride;
     a.budget = BUDGET;
     return a;
@@ -817,7 +853,7 @@ void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint3
     a.scores = scores_dev;
     a.work = persistent ? work_counter : nullptr;
     a.stats = stats;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads).total;
     if ((int)lds > max_lds())
         fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +
                                 " bytes) exceeds the workgroup LDS limit; reduce B*R or k");
@@ -833,7 +869,7 @@ void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint
     if (nq == 0) return;
     QArgs a = make_args(ix, codes_dev, nq, 1);
     a.counts_out = counts_dev;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads).total;
     if ((int)lds > max_lds()) fail(FLINNG_EINVAL, "per-query state exceeds the LDS limit");
     if (ix.cell_bytes == 2)
         launch_q<uint16_t>(a, lds, false, s);

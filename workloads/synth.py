@@ -12,9 +12,16 @@ shaped), URL-like strings as sets of character 3-gram ids (URL shaped) and
 dense non-negative CNN-like embeddings (YFCC100M shaped), plus a small
 Gaussian mixture.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _workers():
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def fmix64(k):
@@ -94,7 +101,9 @@ def dense_relu(N=1_000_000, d=4096, n_centres=10000, p_zero=0.6, sigma=0.1,
     centres, mask = _relu_centres(n_centres, d, p_zero, seed)
     X = np.empty((N, d), dtype=np.uint16)
     assign = np.empty(N, dtype=np.int64)
-    for j, s in enumerate(range(0, N, chunk)):
+
+    def fill(j):
+        s = j * chunk
         e = min(N, s + chunk)
         rng = np.random.default_rng([seed, 1, j])
         a = rng.integers(0, n_centres, e - s)
@@ -103,6 +112,9 @@ def dense_relu(N=1_000_000, d=4096, n_centres=10000, p_zero=0.6, sigma=0.1,
         v = np.where(mask[a], v, np.float32(0.0))
         X[s:e] = f32_to_bf16(v)
         assign[s:e] = a
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(fill, range((N + chunk - 1) // chunk)))
     rq = np.random.default_rng([q_seed, 2])
     qbase = rq.choice(N, size=min(nq, N), replace=False)
     z = rq.standard_normal((len(qbase), d), dtype=np.float32)
@@ -262,16 +274,13 @@ def url(n_templates=1_000_000, dups=4, min_len=20, max_len=120, alphabet=40,
     W = max_len + max_edit + 1
     rng0 = np.random.default_rng([seed, 20])
     key32 = np.uint32(rng0.integers(0, 2**32, dtype=np.uint64)) | np.uint32(1)
-    items_l, offs_l, base = [], [np.zeros(1, dtype=np.uint64)], np.uint64(0)
-    T_all_A, T_all_len = [], []
-    for j, s in enumerate(range(0, n_templates, chunk)):
+    def block(j):
+        s = j * chunk
         n = min(chunk, n_templates - s)
         rng = np.random.default_rng([seed, 21, j])
         lens = rng.integers(min_len, max_len + 1, n)
         A = rng.integers(0, alphabet, (n, W)).astype(np.int16)
         A[np.arange(W)[None, :] >= lens[:, None]] = -1
-        T_all_A.append(A)
-        T_all_len.append(lens)
         blocks_A = [A]
         blocks_L = [lens]
         for c in range(dups):
@@ -283,6 +292,15 @@ def url(n_templates=1_000_000, dups=4, min_len=20, max_len=120, alphabet=40,
         SA = np.stack(blocks_A, axis=1).reshape(n * (dups + 1), W)
         SL = np.stack(blocks_L, axis=1).reshape(n * (dups + 1))
         it, of = _url_items(SA, SL, key32)
+        return A, lens, it, of
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        parts = list(ex.map(block, range((n_templates + chunk - 1) // chunk)))
+    items_l, offs_l, base = [], [np.zeros(1, dtype=np.uint64)], np.uint64(0)
+    T_all_A, T_all_len = [], []
+    for A, lens, it, of in parts:
+        T_all_A.append(A)
+        T_all_len.append(lens)
         items_l.append(it)
         offs_l.append(of[1:] + base)
         base = base + of[-1]

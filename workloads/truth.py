@@ -58,6 +58,45 @@ class JaccardIndex:
         return out_i, out_s
 
 
+def cosine_topk_gpu(X, Q, k, chunk=65536, dense_bf16=False):
+    """Top-k ids by cosine similarity for large dense sets: candidates by a
+    chunked fp32 scan on the GPU (torch), re-scored exactly in FP64 on the
+    host.  X, Q are host arrays (fp32, or bf16 bit patterns if dense_bf16)."""
+    import torch
+
+    def to_f32(a):
+        a = np.ascontiguousarray(a)
+        if dense_bf16:
+            return (a.astype(np.uint32) << np.uint32(16)).view(np.float32)
+        return a.astype(np.float32)
+
+    Qh = to_f32(Q).astype(np.float64)
+    Qd = torch.from_numpy(to_f32(Q)).cuda()
+    Qd = Qd / Qd.norm(dim=1, keepdim=True).clamp_min(1e-30)
+    kk = k + 16
+    best_s = torch.full((Qd.shape[0], 0), -2.0, device="cuda")
+    best_i = torch.zeros((Qd.shape[0], 0), dtype=torch.int64, device="cuda")
+    for s in range(0, X.shape[0], chunk):
+        Xc = torch.from_numpy(to_f32(X[s:s + chunk])).cuda()
+        Xc = Xc / Xc.norm(dim=1, keepdim=True).clamp_min(1e-30)
+        S = Qd @ Xc.T
+        v, i = torch.topk(S, min(kk, S.shape[1]), dim=1)
+        best_s = torch.cat([best_s, v], dim=1)
+        best_i = torch.cat([best_i, i + s], dim=1)
+        v, o = torch.topk(best_s, min(kk, best_s.shape[1]), dim=1)
+        best_s, best_i = v, torch.gather(best_i, 1, o)
+    cand = best_i.cpu().numpy()
+    out_i = np.zeros((Qh.shape[0], k), dtype=np.int64)
+    out_s = np.zeros((Qh.shape[0], k))
+    qn = Qh / np.maximum(np.linalg.norm(Qh, axis=1, keepdims=True), 1e-300)
+    for q in range(Qh.shape[0]):
+        C = to_f32(X[cand[q]]).astype(np.float64)
+        sc = (C / np.maximum(np.linalg.norm(C, axis=1, keepdims=True), 1e-300)) @ qn[q]
+        o = np.lexsort((cand[q], -sc))[:k]
+        out_i[q], out_s[q] = cand[q][o], sc[o]
+    return out_i, out_s
+
+
 def recall_at(found, truth_top1):
     """R1@k: fraction of queries whose exact nearest neighbour is among the k
     returned ids."""

@@ -362,6 +362,111 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_kernel(
     }
 }
 
+// Recheck + pack for bf16 rows read in place (d a multiple of 32, rows
+// 16-byte aligned).  One wavefront per row: its flagged hyperplanes are
+// listed in LDS, then recomputed four at a time, 16 lanes each, with 16-byte
+// loads of 8 bf16 values of the row and of the hyperplane and FP64 partial
+// sums reduced within the 16 lanes.  Same certificate and exact fallback as
+// srp_recheck_pack_kernel.
+__global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
+    const uint16_t *__restrict__ x, uint64_t n, uint32_t d, const uint16_t *__restrict__ w,
+    const uint32_t *__restrict__ bits, const uint32_t *__restrict__ flags, uint32_t Hw,
+    uint32_t H, uint32_t K, uint32_t L, uint32_t *__restrict__ codes,
+    unsigned long long *__restrict__ nexact) {
+    extern __shared__ uint32_t sm[];
+    const int lane = threadIdx.x % 64;
+    const int wave = threadIdx.x / 64;
+    const uint64_t row = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave;
+    if (row >= n) return;
+    const uint32_t per_wave = Hw + (Hw * 32) / 2;  // bit words + uint16 flagged list
+    uint32_t *rb = sm + wave * per_wave;
+    uint16_t *fl = reinterpret_cast<uint16_t *>(rb + Hw);
+    for (uint32_t j = lane; j < Hw; j += 64) rb[j] = bits[row * Hw + j];
+    // list the flagged hyperplanes (wave prefix sums over flag words)
+    uint32_t nf = 0;
+    for (uint32_t j0 = 0; j0 < Hw; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        uint32_t fw = (j < Hw) ? flags[row * Hw + j] : 0u;
+        const uint32_t c = (uint32_t)__popc(fw);
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        uint32_t pos = nf + inc - c;
+        while (fw) {
+            const uint32_t b = (uint32_t)(__ffs(fw) - 1);
+            fw &= fw - 1;
+            const uint32_t h = j * 32 + b;
+            if (h < H) fl[pos] = (uint16_t)h;
+            ++pos;
+        }
+        nf += (uint32_t)__shfl((int)inc, 63, 64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int g = lane >> 4, sl = lane & 15;
+    const uint16_t *xr = x + row * d;
+    for (uint32_t p0 = 0; p0 < nf; p0 += 4) {
+        const uint32_t p = p0 + g;
+        const bool act = p < nf;
+        const uint32_t h = fl[act ? p : nf - 1];
+        if (h >= H) continue;  // never: flags past H are zero
+        const uint16_t *wh = w + (uint64_t)h * d;
+        double v = 0.0, a = 0.0;
+#pragma unroll 4
+        for (uint32_t i = 8 * sl; i < d; i += 128) {
+            const uint4 xv = *reinterpret_cast<const uint4 *>(xr + i);
+            const uint4 wv = *reinterpret_cast<const uint4 *>(wh + i);
+            const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            const uint32_t ws[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double x0 = (double)__uint_as_float(xs[e] << 16);
+                const double x1 = (double)__uint_as_float(xs[e] & 0xFFFF0000u);
+                const double w0 = (double)__uint_as_float(ws[e] << 16);
+                const double w1 = (double)__uint_as_float(ws[e] & 0xFFFF0000u);
+                const double p0_ = x0 * w0, p1_ = x1 * w1;
+                v += p0_;
+                v += p1_;
+                a += fabs(p0_);
+                a += fabs(p1_);
+            }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            v += __shfl_xor(v, o, 64);
+            a += __shfl_xor(a, o, 64);
+        }
+        int sgn = 0;
+        if (act && sl == 0) {
+            if (fabs(v) > 2.0 * (double)d * 0x1p-53 * a) {
+                sgn = v > 0.0 ? 1 : -1;
+            } else {
+                sgn = exact_sign_fixed(x, false, row, d, wh);
+                atomicAdd(nexact, 1ull);
+            }
+            const uint32_t m = 1u << (h & 31);
+            if (sgn > 0)
+                atomicOr(&rb[h >> 5], m);
+            else
+                atomicAnd(&rb[h >> 5], ~m);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t t = lane; t < L; t += 64) {
+        const uint32_t b0 = t * K;
+        const uint32_t wi = b0 / 32, sh = b0 % 32;
+        uint64_t vv = rb[wi];
+        if (sh + K > 32 && wi + 1 < Hw) vv |= (uint64_t)rb[wi + 1] << 32;
+        codes[row * L + t] = (uint32_t)((vv >> sh) & ((K >= 32) ? 0xFFFFFFFFull : ((1ull << K) - 1)));
+    }
+}
+
 // ---------------------------------------------------------------------------
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
               uint64_t *counters_host) {
@@ -425,10 +530,16 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
                            pl, pstride, ld, ix.hyp, dpad, nx.as<float>(), ix.hypnorm, n, H, Hw,
                            gamma, tau_abs, bits.as<uint16_t>(), flags.as<uint16_t>(), nflag);
     FL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(srp_recheck_pack_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
-                       4 * Hw * sizeof(uint32_t), s, xdev, (int)f32, n, d, ix.hyp, dpad,
-                       bits.as<uint32_t>(), flags.as<uint32_t>(), Hw, H, K, L, codes_dev,
-                       nflag + 1);
+    if (inplace)
+        hipLaunchKernelGGL(srp_recheck_pack_vec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
+                           4 * (Hw + Hw * 16) * sizeof(uint32_t), s,
+                           static_cast<const uint16_t *>(xdev), n, d, ix.hyp, bits.as<uint32_t>(),
+                           flags.as<uint32_t>(), Hw, H, K, L, codes_dev, nflag + 1);
+    else
+        hipLaunchKernelGGL(srp_recheck_pack_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
+                           4 * Hw * sizeof(uint32_t), s, xdev, (int)f32, n, d, ix.hyp, dpad,
+                           bits.as<uint32_t>(), flags.as<uint32_t>(), Hw, H, K, L, codes_dev,
+                           nflag + 1);
     FL_CHECK_LAUNCH();
     if (counters_host) {
         unsigned long long c[2];

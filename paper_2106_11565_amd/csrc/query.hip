@@ -337,15 +337,39 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         if (tid == 0) pre[L] = total;
         __syncthreads();
 
-        // ---- 3. count: one increment per listed cell per table
-        for (uint32_t idx = tid; idx < total; idx += QT) {
-            uint32_t lo = 0, hi = L;  // largest t with pre[t] <= idx
-            while (hi - lo > 1) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (pre[mid] <= idx) lo = mid; else hi = mid;
+        // ---- 3. count: one increment per listed cell per table.  The
+        // flattened entry index idx belongs to the last table t with
+        // pre[t] <= idx; a thread's indices only grow, so after one binary
+        // search its table index only moves forward.  Four entries per thread
+        // are loaded before their LDS increments.
+        {
+            uint32_t t = 0;
+            {
+                uint32_t lo = 0, hi = L;
+                const uint32_t idx = tid;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (pre[mid] <= idx) lo = mid; else hi = mid;
+                }
+                t = lo;
             }
-            const uint32_t c = (uint32_t)cells[lstart[lo] + (idx - pre[lo])];
-            atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
+            for (uint32_t base = tid; base < total; base += 4 * QT) {
+                uint32_t c4[4];
+                bool ok[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t idx = base + (uint32_t)u * QT;
+                    ok[u] = idx < total;
+                    c4[u] = 0;
+                    if (ok[u]) {
+                        while (t + 1 < L && pre[t + 1] <= idx) ++t;
+                        c4[u] = (uint32_t)cells[lstart[t] + (idx - pre[t])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (ok[u]) atomicAdd(&cnt32[c4[u] >> 2], 1u << (8 * (c4[u] & 3)));
+            }
         }
         __syncthreads();
 

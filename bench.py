@@ -11,14 +11,21 @@ Extras on the same line: index build time, per-stage times, the decode
 kernel's roofline (algorithmic bytes from the kernel's own work counters /
 its event-timed launch duration, against 8 TB/s), recall@10 against exact
 Jaccard / cosine neighbours on a query sample, the served (continuous
-batching) rate with p50/p99 latency, and the CPU oracle timed on one host core
-over a bounded query sample.
+batching) rate with p50/p99 latency under a burst and under open-loop Poisson
+arrivals, and the CPU oracle timed on one host core over a bounded query
+sample.
+
+--workload c5 keeps the genome and ReLU-embedding indexes resident together
+and sweeps Poisson arrival rates of mixed-family requests (1..512 queries
+each) through the server, beside each family's plain batched rate.
 """
 import argparse
 import ctypes
 import json
 import os
+import queue
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -36,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -44,6 +51,7 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--rates", default="", help="comma-separated Poisson arrival rates (queries/s)")
     return ap.parse_args()
 
 
@@ -61,85 +69,92 @@ def to_dev(torch, a):
     return t.cuda()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the query path is "
-              "replicated per GPU with no exchange, so no multi-GPU figure is produced.",
-              file=sys.stderr)
-        sys.exit(2)
+
+
+class Workload:
+    """One resident index with its queries (host copy and device copy)."""
+
+    def __init__(self, name, scale, torch, fl, configs):
+        t = time.time()
+        self.cfg, self.data, self.queries, self.qbase = configs.make(name, scale=scale)
+        c = self.cfg
+        log(f"generated {c['name']} N={c['N']} nq={c['nq']} in {time.time() - t:.1f}s")
+        self.fam, self.K, self.L, self.R, self.B = c["family"], c["K"], c["L"], c["R"], c["B"]
+        self.b, self.k = c["bucket_bits"], c["k"]
+        self.dense = self.fam in (fl.SRP_F32, fl.SRP_BF16)
+        # inputs resident in HBM
+        if self.dense:
+            data_d = to_dev(torch, self.data)
+            self.q_d = to_dev(torch, self.queries)
+            self.nq = self.q_d.shape[0]
+        else:
+            data_d = (to_dev(torch, self.data[0]), to_dev(torch, self.data[1]))
+            self.q_d = (to_dev(torch, self.queries[0]), to_dev(torch, self.queries[1]))
+            self.nq = self.q_d[1].shape[0] - 1
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        self.index = fl.Index(data_d, self.fam, self.K, self.L, self.R, self.B, configs.INDEX_SEED,
+                              bucket_bits=0 if self.dense else self.b)
+        torch.cuda.synchronize()
+        self.build_s = time.perf_counter() - t
+        del data_d
+        info = self.index.info
+        log(f"built index in {self.build_s:.2f}s: entries={info.list_entries} "
+            f"bytes={info.device_bytes / 2**20:.1f}MiB")
+
+    def host_slice(self, p, n):
+        """Queries p..p+n-1 as a host batch (rows, or items + rebased offsets)."""
+        import numpy as np
+        if self.dense:
+            return self.queries[p:p + n]
+        it, of = self.queries
+        o = of[p:p + n + 1]
+        return (it[int(o[0]):int(o[-1])], (o - o[0]).astype(np.uint64))
+
+
+def plain(w, torch, steps, warmup, persistent):
+    """Event-timed plain batched steps over the device-resident queries."""
     import numpy as np
-    import torch
-    import paper_2106_11565_amd as fl
-    from workloads import configs, truth
-
-    assert torch.cuda.is_available(), "needs a ROCm GPU"
-    torch.cuda.init()
     dev = torch.device("cuda:0")
-
-    t = time.time()
-    cfg, data, queries, qbase = configs.make(args.workload, scale=args.scale)
-    log(f"generated {cfg['name']} N={cfg['N']} nq={cfg['nq']} in {time.time() - t:.1f}s")
-    fam, K, L, R, B, b, k = (cfg["family"], cfg["K"], cfg["L"], cfg["R"], cfg["B"],
-                             cfg["bucket_bits"], cfg["k"])
-    dense = fam in (fl.SRP_F32, fl.SRP_BF16)
-    bb = 0 if dense else b
-
-    # inputs resident in HBM
-    if dense:
-        data_d = to_dev(torch, data)
-        q_d = to_dev(torch, queries)
-        nq = q_d.shape[0]
-    else:
-        data_d = (to_dev(torch, data[0]), to_dev(torch, data[1]))
-        q_d = (to_dev(torch, queries[0]), to_dev(torch, queries[1]))
-        nq = q_d[1].shape[0] - 1
-    torch.cuda.synchronize()
-
-    t = time.perf_counter()
-    gi = fl.Index(data_d, fam, K, L, R, B, configs.INDEX_SEED, bucket_bits=bb)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t
-    info = gi.info
-    log(f"built index in {build_s:.2f}s: entries={info.list_entries} "
-        f"bytes={info.device_bytes / 2**20:.1f}MiB")
-
-    ids_d = torch.empty((nq, k), dtype=torch.int32, device=dev)
-    sc_d = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    ids_d = torch.empty((w.nq, w.k), dtype=torch.int32, device=dev)
+    sc_d = torch.empty((w.nq, w.k), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
-        gi.query(q_d, k, persistent=args.persistent, out=(ids_d, sc_d))
+        w.index.query(w.q_d, w.k, persistent=persistent, out=(ids_d, sc_d))
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    value = nq / (ms_per_step / 1e3)
-    log(f"plain batched: {ms_per_step:.3f} ms/step -> {value:,.0f} q/s (wall {wall:.3f}s)")
-    plain_ids = ids_d.cpu().numpy().view(np.uint32).copy()
-    plain_sc = sc_d.cpu().numpy().view(np.uint32).copy()
+    ms = e0.elapsed_time(e1) / steps
+    ids = ids_d.cpu().numpy().view(np.uint32).copy()
+    sc = sc_d.cpu().numpy().view(np.uint32).copy()
+    return ms, ids, sc, (ids_d, sc_d)
 
-    # ---- stage split: hash alone, decode alone (event-timed on this stream)
+
+def stages(w, torch, fl, steps, persistent, out):
+    """Hash alone and count+decode alone, event-timed on the stream they are
+    launched on, plus the decode kernel's own work counters."""
+    dev = torch.device("cuda:0")
+    ids_d, sc_d = out
     L_ = fl.lib()
-    codes_d = torch.empty((nq, L), dtype=torch.int32, device=dev)
-    inp, keep = fl.make_input(q_d, fam)
+    stream = torch.cuda.current_stream()
+    codes_d = torch.empty((w.nq, w.L), dtype=torch.int32, device=dev)
+    inp, keep = fl.make_input(w.q_d, w.fam)
     sptr = ctypes.c_void_p(stream.cuda_stream)
 
     def hash_once():
-        fl.check(L_.flinng_debug_hash(gi.handle, ctypes.byref(inp), codes_d.data_ptr(), 1, sptr))
+        fl.check(L_.flinng_debug_hash(w.index.handle, ctypes.byref(inp), codes_d.data_ptr(), 1, sptr))
 
     def decode_once(stats=None):
-        fl.check(L_.flinng_query_codes(gi.handle, codes_d.data_ptr(), nq, k, ids_d.data_ptr(),
-                                       sc_d.data_ptr(), int(args.persistent),
+        fl.check(L_.flinng_query_codes(w.index.handle, codes_d.data_ptr(), w.nq, w.k,
+                                       ids_d.data_ptr(), sc_d.data_ptr(), int(persistent),
                                        stats.data_ptr() if stats is not None else None, sptr))
 
     def timed(fn, n):
@@ -154,130 +169,273 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(z) / n
 
-    hash_ms = timed(hash_once, args.steps)
-    decode_ms = timed(decode_once, args.steps)
+    hash_ms = timed(hash_once, steps)
+    decode_ms = timed(decode_once, steps)
     stats = torch.zeros(5, dtype=torch.int64, device=dev)
     decode_once(stats)
     torch.cuda.synchronize()
     st = [int(v) for v in stats.cpu().tolist()]
-    assert np.array_equal(ids_d.cpu().numpy().view(np.uint32), plain_ids), "decode-only != full path"
     # algorithmic bytes of one decode launch: codes (L*4) and bucket offset
     # pairs (L*8) per query, every list entry read, each member id read by the
     # final decode pass (4 B), the R group ids of each candidate it gathers
     # (2R B), and k ids + scores out
-    cb = info.cell_id_bytes
-    alg_bytes = nq * L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * R + nq * k * 8
-    achieved = alg_bytes / (decode_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    cb = w.index.info.cell_id_bytes
+    alg = w.nq * w.L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * w.R + w.nq * w.k * 8
+    ach = alg / (decode_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "query_kernel (count + threshold + decode)",
-            "alg_bytes_per_launch": int(alg_bytes), "launch_ms": round(decode_ms, 4),
-            "list_entries": st[0], "member_ids_all_passes": st[1],
-            "member_ids_final": st[2], "passes": st[3], "group_rows_gathered": st[4]}
-    log(f"hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg_bytes / 1e6:.1f} MB "
-        f"-> {achieved:.0f} GB/s; stats {st}")
+            "alg_bytes_per_launch": int(alg), "launch_ms": round(decode_ms, 4),
+            "list_entries": st[0], "member_ids_all_passes": st[1], "member_ids_final": st[2],
+            "passes": st[3], "group_rows_gathered": st[4]}
+    log(f"hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg / 1e6:.1f} MB -> "
+        f"{ach:.0f} GB/s; stats {st}")
+    return hash_ms, decode_ms, roof
+
+
+def recall(w, fl, ids, nq_sample):
+    from workloads import truth
+    t = time.time()
+    ns = min(nq_sample, w.nq)
+    if w.dense:
+        ti, _ = truth.cosine_topk_gpu(w.data, w.queries[:ns], 10, dense_bf16=(w.fam == fl.SRP_BF16))
+    else:
+        ji = truth.JaccardIndex(w.data[0], w.data[1])
+        ti, _ = ji.topk(w.queries[0], w.queries[1][:ns + 1], 10)
+    r1 = truth.recall_at(ids[:ns, :10], ti[:, 0])
+    log(f"R1@10 = {r1:.4f} on {ns} queries ({time.time() - t:.1f}s)")
+    return {"R1@10": round(r1, 4), "queries": ns}
+
+
+def sweep_requests(w, sizes):
+    """Requests (slot 0, batch, size, first query) covering the whole query
+    set in order, with the given sizes (cycled) or U{1..512}."""
+    import numpy as np
+    rng = np.random.default_rng(4)
+    out, pos, i = [], 0, 0
+    while pos < w.nq:
+        n = int(sizes[i % len(sizes)]) if sizes is not None else int(rng.integers(1, 513))
+        n = min(n, w.nq - pos)
+        out.append((0, w.host_slice(pos, n), n, pos))
+        pos += n
+        i += 1
+    return out
+
+
+def poisson_requests(workloads, n_req, seed, sizes=None):
+    """n_req requests (slot, batch, size, first query): the slot uniform over
+    the workloads, the size U{1..512} unless `sizes` is given (cycled); each
+    workload's queries are taken in order, wrapping around."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pos = [0] * len(workloads)
+    out = []
+    for i in range(n_req):
+        s = int(rng.integers(0, len(workloads))) if len(workloads) > 1 else 0
+        w = workloads[s]
+        n = int(sizes[i % len(sizes)]) if sizes is not None else int(rng.integers(1, 513))
+        n = min(n, w.nq)
+        if pos[s] + n > w.nq:
+            pos[s] = 0
+        out.append((s, w.host_slice(pos[s], n), n, pos[s]))
+        pos[s] += n
+    return out
+
+
+def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False):
+    """Submit `reqs` to a fresh server (after a warm-up burst of the first 64),
+    open loop: exponential inter-arrival gaps with mean (mean request size /
+    rate_qps), or all at once when rate_qps is 0.  A second thread waits for the tickets in order.  Returns
+    the achieved rate (queries / time from first submit to last completion),
+    the server's latency percentiles (completion - submit) and whether every
+    result equals the plain batched result for the same queries."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    mean = float(np.mean([r[2] for r in reqs]))
+    arrivals = (np.cumsum(rng.exponential(mean / rate_qps, len(reqs))) if rate_qps > 0
+                else np.zeros(len(reqs)))
+    srv = fl.Server([w.index for w in workloads], mem_budget=8 << 30, max_inflight=4,
+                    max_batch=4096, persistent=persistent)
+    # warm-up: one burst sizes every stream's workspace; statistics restart
+    # after it so that they describe the steady state
+    warm = [srv.submit(r[0], r[1], workloads[r[0]].k) + (workloads[r[0]].k,) for r in reqs[:64]]
+    for tk, n, k in warm:
+        srv.wait(tk, n, k)
+    srv.reset_stats()
+    tq = queue.Queue()
+    state = {"same": True, "t_last": 0.0, "err": None}
+
+    def waiter():
+        try:
+            while True:
+                item = tq.get()
+                if item is None:
+                    return
+                tk, n, k, (s, _, _, p) = item
+                ids, sc = srv.wait(tk, n, k)
+                state["t_last"] = time.perf_counter()
+                ref_i, ref_s = refs[s]
+                state["same"] &= bool(np.array_equal(ids, ref_i[p:p + n]) and
+                                      np.array_equal(sc, ref_s[p:p + n]))
+        except Exception as e:  # surfaced after join
+            state["err"] = e
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    lag = 0.0
+    try:
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            target = t0 + arrivals[i]
+            now = time.perf_counter()
+            while now < target:
+                if target - now > 0.002:
+                    time.sleep(target - now - 0.001)
+                now = time.perf_counter()
+            lag = max(lag, now - target)
+            k = workloads[r[0]].k
+            tk, n = srv.submit(r[0], r[1], k)
+            tq.put((tk, n, k, r))
+    finally:
+        tq.put(None)
+        th.join()
+    if state["err"] is not None:
+        raise state["err"]
+    wall = state["t_last"] - t0
+    st = srv.stats()
+    srv.close()
+    nq = sum(r[2] for r in reqs)
+    return {"offered_qps": rate_qps if rate_qps > 0 else "burst",
+            "achieved_qps": round(nq / wall, 1), "p50_ms": round(st["p50_ms"], 3),
+            "p99_ms": round(st["p99_ms"], 3), "requests": len(reqs), "queries": nq,
+            "batches": st["batches"], "mean_batch": round(st["mean_batch"], 1),
+            "max_submit_lag_ms": round(lag * 1e3, 3), "identical_to_plain": bool(state["same"])}
+
+
+def cpu_baseline(w, ids, sc, seconds):
+    """The oracle on one host core over the first queries of the batch."""
+    import numpy as np
+    import oracle
+    from workloads import configs
+    t = time.time()
+    ofam = {0: oracle.SRP_F32, 1: oracle.SRP_BF16, 2: oracle.MINHASH_U32,
+            3: oracle.MINHASH_U64}[w.fam]
+    oi = oracle.OracleIndex(ofam, w.data, w.K, w.L, w.R, w.B, configs.INDEX_SEED,
+                            bucket_bits=None if w.dense else w.b)
+    log(f"oracle index built in {time.time() - t:.1f}s (not timed)")
+    done, agree = 0, True
+    t0 = time.perf_counter()
+    while done < w.nq and time.perf_counter() - t0 < seconds:
+        n = min(50, w.nq - done)
+        wi, ws = oi.query(w.host_slice(done, n), w.k, literal=True)
+        agree &= np.array_equal(wi, ids[done:done + n]) and np.array_equal(ws, sc[done:done + n])
+        done += n
+    cpu_s = time.perf_counter() - t0
+    log(f"oracle: {done} queries in {cpu_s:.1f}s -> {done / cpu_s:.2f} q/s; agree={agree}")
+    return {"value": round(done / cpu_s, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {w.nq} queries against the full-size oracle index "
+                      "(hash, reverse-index counts, literal Algorithm 3 walk; index build "
+                      "not timed)",
+            "gpu_matches_oracle_on_sample": bool(agree)}
+
+
+METRIC = "queries/s at recall@10>=0.9, served vs plain batched; p50/p99 query latency"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the query path is "
+              "replicated per GPU with no exchange, so no multi-GPU figure is produced.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2106_11565_amd as fl
+    from workloads import configs
+
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    torch.cuda.init()
+    if args.workload == "c5":
+        return main_mixed(args, torch, fl, configs)
+
+    w = Workload(args.workload, args.scale, torch, fl, configs)
+    ms, ids, sc, out_d = plain(w, torch, args.steps, args.warmup, args.persistent)
+    value = w.nq / (ms / 1e3)
+    log(f"plain batched: {ms:.3f} ms/step -> {value:,.0f} q/s")
+    hash_ms, decode_ms, roof = stages(w, torch, fl, args.steps, args.persistent, out_d)
+    assert np.array_equal(out_d[0].cpu().numpy().view(np.uint32), ids), "decode-only != full path"
 
     out = {
-        "metric": "queries/s at recall@10>=0.9, served vs plain batched; p50/p99 query latency",
-        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": ("bf16+f32acc+f64" if fam == fl.SRP_BF16 else "f32+f64") if dense else "u64",
+        "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": ("bf16+f32acc+f64" if w.fam == fl.SRP_BF16 else "f32+f64") if w.dense else "u64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "N": cfg["N"], "nq": nq, "K": K, "L": L, "R": R,
-                   "B": B, "bucket_bits": b, "k": k, "persistent": bool(args.persistent)},
-        "build_s": round(build_s, 3),
+        "config": {"workload": w.cfg["name"], "N": w.cfg["N"], "nq": w.nq, "K": w.K, "L": w.L,
+                   "R": w.R, "B": w.B, "bucket_bits": w.b, "k": w.k,
+                   "persistent": bool(args.persistent)},
+        "build_s": round(w.build_s, 3),
         "stages_ms": {"hash": round(hash_ms, 4), "count_decode": round(decode_ms, 4)},
         "roofline": roof,
     }
-
-    # ---- recall@10 on a query sample (exact neighbours by brute force)
     if not args.no_recall:
-        t = time.time()
-        ns = min(args.recall_queries, nq)
-        if dense:
-            ti, _ = truth.cosine_topk_gpu(data, queries[:ns], 10,
-                                          dense_bf16=(fam == fl.SRP_BF16))
-        else:
-            ji = truth.JaccardIndex(data[0], data[1])
-            ti, _ = ji.topk(queries[0], queries[1][:ns + 1], 10)
-        r1 = truth.recall_at(plain_ids[:ns, :10], ti[:, 0])
-        out["recall"] = {"R1@10": round(r1, 4), "queries": ns}
-        log(f"R1@10 = {r1:.4f} on {ns} queries ({time.time() - t:.1f}s)")
+        out["recall"] = recall(w, fl, ids, args.recall_queries)
 
-    # ---- served: continuous batching of uneven requests (sizes 1..512)
     if not args.no_serve:
-        if "group_sizes" in cfg:
-            sizes = [int(v) for v in cfg["group_sizes"]]   # the workload's uneven groups
-        else:
-            rng = np.random.default_rng(4)
-            sizes = []
-            tot = 0
-            while tot < nq:
-                s_ = int(min(rng.integers(1, 513), nq - tot))
-                sizes.append(s_)
-                tot += s_
-        srv = fl.Server([gi], mem_budget=8 << 30, max_inflight=4, max_batch=4096,
-                        persistent=args.persistent)
-        reqs = []
-        pos = 0
-        for s_ in sizes:
-            if dense:
-                qq = queries[pos:pos + s_]
-            else:
-                it, of = queries
-                o = of[pos:pos + s_ + 1]
-                qq = (it[int(o[0]):int(o[-1])], (o - o[0]).astype(np.uint64))
-            reqs.append((pos, s_, qq))
-            pos += s_
-        t0 = time.perf_counter()
-        tickets = [(p_, s_, srv.submit(0, qq, k)[0]) for p_, s_, qq in reqs]
-        same = True
-        for p_, s_, tk in tickets:
-            i_, sc_ = srv.wait(tk, s_, k)
-            same &= np.array_equal(i_, plain_ids[p_:p_ + s_]) and np.array_equal(sc_, plain_sc[p_:p_ + s_])
-        wall_s = time.perf_counter() - t0
-        stt = srv.stats()
-        srv.close()
-        out["served"] = {"qps": round(nq / wall_s, 1), "p50_ms": round(stt["p50_ms"], 3),
-                         "p99_ms": round(stt["p99_ms"], 3), "requests": len(sizes),
-                         "mean_batch": round(stt["mean_batch"], 1), "batches": stt["batches"],
-                         "identical_to_plain": bool(same), "arrivals": "burst (all at t=0)"}
-        log(f"served: {nq / wall_s:,.0f} q/s p50 {stt['p50_ms']:.2f} ms p99 {stt['p99_ms']:.2f} ms "
-            f"batches {stt['batches']} identical={same}")
+        sizes = w.cfg.get("group_sizes")
+        burst = serve_run(fl, [w], sweep_requests(w, sizes), 0, 5, [(ids, sc)], args.persistent)
+        log(f"served burst: {burst}")
+        rates = [float(r) for r in args.rates.split(",")] if args.rates else [1e5, 1e6]
+        pois = []
+        for i, rate in enumerate(rates):
+            n_req = int(max(40, min(3000, rate * 1.0 / 256.5)))
+            rr = poisson_requests([w], n_req, 6 + i, sizes)
+            pois.append(serve_run(fl, [w], rr, rate, 7 + i, [(ids, sc)], args.persistent))
+            log(f"served Poisson @ {rate:,.0f} q/s: {pois[-1]}")
+        out["served"] = {"plain_qps": round(value, 1), "burst": burst, "poisson": pois}
 
-    # ---- CPU baseline: the oracle, one core, bounded query sample
     if not args.no_cpu:
-        import oracle
-        t = time.time()
-        ofam = {0: oracle.SRP_F32, 1: oracle.SRP_BF16, 2: oracle.MINHASH_U32,
-                3: oracle.MINHASH_U64}[fam]
-        oi = oracle.OracleIndex(ofam, data, K, L, R, B, configs.INDEX_SEED,
-                                bucket_bits=None if dense else b)
-        log(f"oracle index built in {time.time() - t:.1f}s (not timed)")
-        done = 0
-        agree = True
-        t0 = time.perf_counter()
-        chunk = 50
-        while done < nq and time.perf_counter() - t0 < args.cpu_seconds:
-            n = min(chunk, nq - done)
-            if dense:
-                qq = queries[done:done + n]
-            else:
-                it, of = queries
-                o = of[done:done + n + 1]
-                qq = (it[int(o[0]):int(o[-1])], (o - o[0]).astype(np.uint64))
-            wi, ws = oi.query(qq, k, literal=True)
-            agree &= np.array_equal(wi, plain_ids[done:done + n]) and np.array_equal(ws, plain_sc[done:done + n])
-            done += n
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(done / cpu_s, 2), "unit": "queries/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {done} of {nq} queries against the full-size "
-                                         "oracle index (hash, reverse-index counts, literal "
-                                         "Algorithm 3 walk; index build not timed)",
-                               "gpu_matches_oracle_on_sample": bool(agree)}
-        log(f"oracle: {done} queries in {cpu_s:.1f}s -> {done / cpu_s:.2f} q/s; agree={agree}")
+        out["cpu_baseline"] = cpu_baseline(w, ids, sc, args.cpu_seconds)
 
+    print(json.dumps(out), flush=True)
+
+
+def main_mixed(args, torch, fl, configs):
+    """Genome reads (MinHash) and ReLU embeddings (SRP) resident together:
+    each family's plain batched rate, then a sweep of Poisson arrival rates of
+    mixed-family requests through one server, and a burst (saturation)."""
+    ws = [Workload("c2", args.scale, torch, fl, configs),
+          Workload("c3", args.scale, torch, fl, configs)]
+    plain_res, refs = [], []
+    for w in ws:
+        ms, ids, sc, _ = plain(w, torch, args.steps, args.warmup, False)
+        plain_res.append({"workload": w.cfg["name"], "nq": w.nq, "ms_per_step": round(ms, 4),
+                          "qps": round(w.nq / (ms / 1e3), 1)})
+        refs.append((ids, sc))
+        log(f"plain {w.cfg['name']}: {w.nq / (ms / 1e3):,.0f} q/s")
+    # half the queries from each family, each family batched on its own
+    mixed_plain = sum(w.nq for w in ws) / sum(r["ms_per_step"] / 1e3 for r in plain_res)
+    rates = ([float(r) for r in args.rates.split(",")] if args.rates else
+             [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6, 2e6])
+    sweep = []
+    for i, rate in enumerate(rates):
+        n_req = int(max(30, min(3000, rate * 1.0 / 256.5)))
+        r = serve_run(fl, ws, poisson_requests(ws, n_req, 100 + i), rate, 200 + i, refs)
+        sweep.append(r)
+        log(f"served mixed Poisson @ {rate:,.0f} q/s: {r}")
+    burst = serve_run(fl, ws, poisson_requests(ws, 200, 99), 0, 98, refs)
+    log(f"served mixed burst: {burst}")
+    out = {
+        "metric": METRIC, "value": burst["achieved_qps"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 | bf16+f32acc+f64", "data": "synthetic",
+        "config": {"workload": "mixed serving: genome_reads_1M_minhash + relu_embed_1M_d4096_bf16",
+                   "requests": "Poisson arrivals, sizes U{1..512}, family 50/50, k=10"},
+        "plain": plain_res, "plain_mixed_qps": round(mixed_plain, 1),
+        "served_poisson": sweep, "served_burst": burst,
+    }
     print(json.dumps(out), flush=True)
 
 

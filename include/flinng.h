@@ -184,14 +184,18 @@ int flinng_index_export(const flinng_index *idx, uint64_t *offsets,
 typedef struct flinng_server flinng_server;
 
 typedef struct flinng_serve_config {
-    uint64_t mem_budget;      /* device bytes the server may hold for
-                                 in-flight batches (inputs, outputs, scratch) */
+    uint64_t mem_budget;      /* device bytes the batch workspaces of all
+                                 streams may hold together (staged inputs,
+                                 codes, results, hash scratch); a workspace
+                                 is kept between batches and given back when
+                                 another stream needs the room                */
     uint32_t max_inflight;    /* batches on the GPU at once (streams), 1..16  */
     uint32_t max_batch;       /* queries per launched batch, >= 1             */
     uint32_t max_queue;       /* queued requests before submit refuses        */
     uint32_t persistent;      /* launch batches with the persistent grid      */
-    uint64_t linger_ns;       /* wait this long for more requests when a
-                                 slot is free but the batch is not full       */
+    uint64_t linger_ns;       /* hold a batch that is not full until its
+                                 oldest request has waited this long (0: launch
+                                 as soon as a stream is free)                 */
 } flinng_serve_config;
 
 typedef struct flinng_serve_stats {
@@ -200,7 +204,7 @@ typedef struct flinng_serve_stats {
     double qps;               /* completed queries / wall_s                   */
     double p50_ms, p99_ms, max_ms; /* completion - submit latency per request */
     double mean_batch;        /* queries per launched batch                   */
-    uint64_t peak_mem_bytes;  /* peak admitted in-flight memory               */
+    uint64_t peak_mem_bytes;  /* peak device bytes held by the workspaces     */
 } flinng_serve_stats;
 
 /* Create a server over n_idx resident indexes (borrowed; they must outlive
@@ -224,6 +228,11 @@ int flinng_serve_wait(flinng_server *srv, uint64_t ticket, uint32_t *ids,
 int flinng_serve_poll(flinng_server *srv, uint64_t ticket);
 
 int flinng_serve_stats_get(flinng_server *srv, flinng_serve_stats *st);
+
+/* Start the statistics afresh (counters, latencies, wall clock; the peak
+ * memory restarts at what the workspaces hold now), e.g. after a warm-up.
+ * Requests in flight at the call are counted when they complete. */
+int flinng_serve_stats_reset(flinng_server *srv);
 
 /* Drain in-flight work, then stop the scheduler and free the server.
  * Requests not yet waited on are discarded. */

@@ -121,15 +121,21 @@ class Server:
                                         ctypes.byref(h)))
         self._h = h
 
+    def _family(self, slot):
+        # an out-of-range slot is marshalled as slot 0's family so that the
+        # library itself rejects it
+        ok = isinstance(slot, int) and 0 <= slot < len(self._indexes)
+        return self._indexes[slot if ok else 0].family
+
     def submit(self, slot, q, k):
-        inp, keep = make_input(q, self._indexes[slot].family)
+        inp, keep = make_input(q, self._family(slot))
         t = ctypes.c_uint64()
         check(lib().flinng_serve_submit(self._h, slot, ctypes.byref(inp), k, ctypes.byref(t)))
         return t.value, int(inp.count)
 
     def try_submit(self, slot, q, k):
         """Like submit, but returns (None, rc) instead of raising on refusal."""
-        inp, keep = make_input(q, self._indexes[slot].family)
+        inp, keep = make_input(q, self._family(slot))
         t = ctypes.c_uint64()
         rc = lib().flinng_serve_submit(self._h, slot, ctypes.byref(inp), k, ctypes.byref(t))
         return (t.value if rc == 0 else None), rc
@@ -151,6 +157,9 @@ class Server:
         st = ServeStats()
         check(lib().flinng_serve_stats_get(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+    def reset_stats(self):
+        check(lib().flinng_serve_stats_reset(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -84,6 +84,7 @@ def lib():
             "flinng_serve_wait": (ctypes.c_int, [c_vp, c_u64, c_vp, c_vp, c_i64]),
             "flinng_serve_poll": (ctypes.c_int, [c_vp, c_u64]),
             "flinng_serve_stats_get": (ctypes.c_int, [c_vp, P(ServeStats)]),
+            "flinng_serve_stats_reset": (ctypes.c_int, [c_vp]),
             "flinng_serve_destroy": (None, [c_vp]),
         }
         for name, (res, args) in sig.items():

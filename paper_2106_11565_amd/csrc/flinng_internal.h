@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/flinng.h"
 
@@ -109,19 +110,65 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// A device region owned by the caller, handed out by a bump pointer in
+// 256-byte aligned pieces.  Running past its end is an internal sizing error.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+    void *take(size_t bytes) {
+        if (bytes == 0) return nullptr;
+        const size_t b = round(bytes);
+        if (used + b > cap) fail(FLINNG_EDEVICE, "internal: batch workspace undersized");
+        void *p = base + used;
+        used += b;
+        return p;
+    }
+};
+
+// Scratch of one call: carved from an arena when one is given, otherwise
+// allocated on the stream and freed on it when the Scratch goes away.
+struct Scratch {
+    Arena *arena;
+    hipStream_t stream;
+    std::vector<DevBuf> owned;
+    Scratch(Arena *a, hipStream_t s) : arena(a), stream(s) {}
+    template <class T = void> T *get(size_t bytes) {
+        if (bytes == 0) return nullptr;
+        if (arena) return static_cast<T *>(arena->take(bytes));
+        owned.emplace_back(bytes, stream);
+        return static_cast<T *>(owned.back().ptr);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Hashing (hash_srp.hip, hash_minhash.hip).  All write codes[n][L] uint32.
 void srp_make_hyperplanes(Index &ix, hipStream_t s);
 // Returns (rechecked, exact) counts when counters != nullptr (synchronizes).
+// Scratch comes from ws when given (srp_scratch_bytes bounds what it takes).
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
-              hipStream_t s, uint64_t *counters_host);
+              hipStream_t s, uint64_t *counters_host, Arena *ws = nullptr);
+// Upper bound of the scratch srp_hash takes for n rows already on the device.
+size_t srp_scratch_bytes(const Index &ix, uint64_t n);
 void minhash_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
                   hipStream_t s, double mean_hint = -1.0);
-// mean_hint: mean items per set of a device-resident set batch (<= 0: unknown)
+// mean_hint: mean items per set of a device-resident set batch (<= 0: unknown).
+// Device-resident inputs take no scratch beyond ws (MinHash takes none).
 void hash_batch(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
-                hipStream_t s, uint64_t *counters_host, double mean_hint = -1.0);
-// Device bytes one batch of nq queries (nitems set items) needs in flight.
+                hipStream_t s, uint64_t *counters_host, double mean_hint = -1.0,
+                Arena *ws = nullptr);
+// Device bytes one served batch of nq queries (nitems set items) occupies:
+// staged input, codes, results and hash scratch, as the server carves them.
 uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k);
+
+// Segment copies by kernel (stage.hip): each segment copies `bytes` from
+// src to dst, both device-visible addresses (device memory, or mapped pinned
+// host memory).  Segments must not overlap their destinations.
+struct CopySeg {
+    uint64_t src, dst, bytes;
+};
+constexpr int MAX_COPY_SEGS = 128;  // per launch (kernel-argument space)
+void copy_segments(const CopySeg *segs, size_t nseg, hipStream_t s);
 
 // Sorting and scans (radix.hip).
 void device_exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n,

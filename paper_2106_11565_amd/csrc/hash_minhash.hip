@@ -145,9 +145,9 @@ void minhash_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, 
 }
 
 void hash_batch(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
-                uint64_t *counters_host, double mean_hint) {
+                uint64_t *counters_host, double mean_hint, Arena *ws) {
     if (is_dense(ix.p.family))
-        srp_hash(ix, in, codes_dev, s, counters_host);
+        srp_hash(ix, in, codes_dev, s, counters_host, ws);
     else
         minhash_hash(ix, in, codes_dev, s, mean_hint);
 }

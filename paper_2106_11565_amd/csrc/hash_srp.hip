@@ -96,10 +96,19 @@ void srp_make_hyperplanes(Index &ix, hipStream_t s) {
 template <bool F32>
 __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d,
                             uint32_t dpad, uint16_t *__restrict__ planes,
-                            float *__restrict__ nx) {
+                            float *__restrict__ nx, uint32_t *__restrict__ bits,
+                            uint32_t *__restrict__ flags, uint32_t Hw,
+                            unsigned long long *__restrict__ ctr) {
     uint64_t row = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     uint32_t lane = threadIdx.x % 64;
     if (row >= n) return;
+    // clear this row's sign and flag words (the projection kernel leaves the
+    // words past the last hyperplane untouched) and the flag counters
+    for (uint32_t w = lane; w < Hw; w += 64) {
+        bits[row * Hw + w] = 0u;
+        flags[row * Hw + w] = 0u;
+    }
+    if (row == 0 && lane < 2) ctr[lane] = 0ull;
     const uint64_t plane_stride = n * dpad;
     float s = 0.f;
     for (uint32_t i = lane; i < dpad; i += 64) {
@@ -468,8 +477,15 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
 }
 
 // ---------------------------------------------------------------------------
+size_t srp_scratch_bytes(const Index &ix, uint64_t n) {
+    const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
+    const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
+    return Arena::round((size_t)nsplit * n * ix.dpad * 2) + Arena::round(n * 4) +
+           2 * Arena::round(n * Hw * 4) + Arena::round(16);
+}
+
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
-              uint64_t *counters_host) {
+              uint64_t *counters_host, Arena *ws) {
     const uint64_t n = in.count;
     if (n == 0) return;
     const uint32_t d = ix.p.dim, dpad = ix.dpad;
@@ -477,8 +493,9 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     const uint32_t Hw = (H + 31) / 32;
     const bool f32 = ix.p.family == FLINNG_SRP_F32;
     const int nsplit = f32 ? 3 : 1;
+    Scratch sc(ws, s);
 
-    // stage values on the device
+    // stage values on the device (host inputs never come with an arena)
     const size_t esz = f32 ? 4 : 2;
     const void *xdev = in.values;
     DevBuf xcopy;
@@ -488,26 +505,22 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         xdev = xcopy.ptr;
     }
     const bool inplace = !f32 && (d == dpad) && ((reinterpret_cast<uintptr_t>(xdev) & 15) == 0);
-    DevBuf planes(inplace ? 0 : (size_t)nsplit * n * dpad * 2, s);
-    DevBuf nx(n * 4, s);
-    DevBuf bits(n * Hw * 4, s), flags(n * Hw * 4, s);
-    DevBuf ctr(16, s);
-    FL_HIP(hipMemsetAsync(ctr.ptr, 0, 16, s));
-    // words past H (when H is not a multiple of 32) are never written by the
-    // MFMA epilogue; keep them zero so no flag points past the last hyperplane
-    FL_HIP(hipMemsetAsync(bits.ptr, 0, n * Hw * 4, s));
-    FL_HIP(hipMemsetAsync(flags.ptr, 0, n * Hw * 4, s));
+    uint16_t *planes = sc.get<uint16_t>(inplace ? 0 : (size_t)nsplit * n * dpad * 2);
+    float *nx = sc.get<float>(n * 4);
+    uint32_t *bits = sc.get<uint32_t>(n * Hw * 4);
+    uint32_t *flags = sc.get<uint32_t>(n * Hw * 4);
+    unsigned long long *ctr = sc.get<unsigned long long>(16);
     {
         dim3 grid((unsigned)((n + 3) / 4));
         if (f32)
-            hipLaunchKernelGGL(prep_kernel<true>, grid, dim3(256), 0, s, xdev, n, d, dpad,
-                               planes.as<uint16_t>(), nx.as<float>());
+            hipLaunchKernelGGL(prep_kernel<true>, grid, dim3(256), 0, s, xdev, n, d, dpad, planes,
+                               nx, bits, flags, Hw, ctr);
         else
             hipLaunchKernelGGL(prep_kernel<false>, grid, dim3(256), 0, s, xdev, n, d, dpad,
-                               inplace ? nullptr : planes.as<uint16_t>(), nx.as<float>());
+                               inplace ? nullptr : planes, nx, bits, flags, Hw, ctr);
         FL_CHECK_LAUNCH();
     }
-    const uint16_t *pl = inplace ? static_cast<const uint16_t *>(xdev) : planes.as<uint16_t>();
+    const uint16_t *pl = inplace ? static_cast<const uint16_t *>(xdev) : planes;
     const uint32_t ld = inplace ? d : dpad;
     const uint64_t pstride = (uint64_t)n * dpad;
 
@@ -520,30 +533,31 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     constexpr int MR = 4, NR = 4, WM = 2, WN = 2;
     dim3 grid((H + 16 * NR * WN - 1) / (16 * NR * WN),
               (unsigned)((n + 16 * MR * WM - 1) / (16 * MR * WM)));
-    unsigned long long *nflag = ctr.as<unsigned long long>();
+    unsigned long long *nflag = ctr;
     if (nsplit == 3)
         hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 3>), grid, dim3(64 * WM * WN), 0, s,
-                           pl, pstride, ld, ix.hyp, dpad, nx.as<float>(), ix.hypnorm, n, H, Hw,
-                           gamma, tau_abs, bits.as<uint16_t>(), flags.as<uint16_t>(), nflag);
+                           pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
+                           reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
+                           nflag);
     else
         hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 1>), grid, dim3(64 * WM * WN), 0, s,
-                           pl, pstride, ld, ix.hyp, dpad, nx.as<float>(), ix.hypnorm, n, H, Hw,
-                           gamma, tau_abs, bits.as<uint16_t>(), flags.as<uint16_t>(), nflag);
+                           pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
+                           reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
+                           nflag);
     FL_CHECK_LAUNCH();
     if (inplace)
         hipLaunchKernelGGL(srp_recheck_pack_vec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
                            4 * (Hw + Hw * 16) * sizeof(uint32_t), s,
-                           static_cast<const uint16_t *>(xdev), n, d, ix.hyp, bits.as<uint32_t>(),
-                           flags.as<uint32_t>(), Hw, H, K, L, codes_dev, nflag + 1);
+                           static_cast<const uint16_t *>(xdev), n, d, ix.hyp, bits, flags, Hw, H,
+                           K, L, codes_dev, nflag + 1);
     else
         hipLaunchKernelGGL(srp_recheck_pack_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
-                           4 * Hw * sizeof(uint32_t), s, xdev, (int)f32, n, d, ix.hyp, dpad,
-                           bits.as<uint32_t>(), flags.as<uint32_t>(), Hw, H, K, L, codes_dev,
-                           nflag + 1);
+                           4 * Hw * sizeof(uint32_t), s, xdev, (int)f32, n, d, ix.hyp, dpad, bits,
+                           flags, Hw, H, K, L, codes_dev, nflag + 1);
     FL_CHECK_LAUNCH();
     if (counters_host) {
         unsigned long long c[2];
-        FL_HIP(hipMemcpyAsync(c, ctr.ptr, 16, hipMemcpyDeviceToHost, s));
+        FL_HIP(hipMemcpyAsync(c, ctr, 16, hipMemcpyDeviceToHost, s));
         FL_HIP(hipStreamSynchronize(s));
         counters_host[0] = c[0];
         counters_host[1] = c[1];

@@ -4,8 +4,13 @@
 // queued.  One scheduler thread keeps up to max_inflight batches on the GPU,
 // one per HIP stream (all at the default priority): whenever a stream is free
 // and the memory budget admits it, it coalesces queued requests of the same
-// (index, k) into one batch, stages them through a pinned buffer, enqueues
-// hash + count + decode and the copy back, and records an event.  Batches of
+// (index, k) into one batch and enqueues a copy kernel that pulls every
+// request's payload from pinned host memory, hash + count + decode, a copy
+// kernel that writes the results into pinned host memory, and an event.  Each
+// stream keeps its device workspace (staged input, codes, results, hash
+// scratch) and pinned buffers between batches, so a steady stream of batches
+// allocates nothing; the workspaces of all streams together stay within the
+// memory budget, idle streams giving theirs back when another needs room.  Batches of
 // different indexes (hash families) run concurrently on different streams.
 // Completed batches are detected by event query; each request's results are
 // sliced out and its latency (completion - submit, host steady clock) is
@@ -18,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -29,50 +35,164 @@ namespace flinng {
 
 using Clock = std::chrono::steady_clock;
 
-uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k) {
-    const uint64_t L = ix.p.L;
-    uint64_t b = nq * L * 4 + 2 * nq * (uint64_t)k * 4 + 4 + 256;
-    if (is_dense(ix.p.family)) {
-        const bool f32 = ix.p.family == FLINNG_SRP_F32;
-        const uint64_t H = L * ix.p.K, Hw = (H + 31) / 32;
-        b += nq * ix.p.dim * (f32 ? 4 : 2);                 // staged rows
-        b += (f32 ? 3 : 1) * nq * (uint64_t)ix.dpad * 2;    // operand planes
-        b += nq * 4 + 2 * nq * Hw * 4 + 16;                 // norms, bits, flags
-    } else {
-        b += nitems * (ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4) + (nq + 1) * 8;
-    }
+// Layout of one served batch inside its lane's device workspace (byte
+// offsets, each piece 256-byte aligned).  The staged input holds the values,
+// then (sets) the rebased offsets at an 8-byte aligned position, so one copy
+// moves both; ids and scores are adjacent so one copy brings both back.
+struct BatchPlan {
+    size_t in = 0, in_bytes = 0, offs = 0;
+    size_t codes = 0, out = 0, work = 0, hash = 0, total = 0;
+};
+
+static BatchPlan plan_batch(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k) {
+    BatchPlan b;
+    const bool dense = is_dense(ix.p.family);
+    const size_t vbytes = dense ? nq * (size_t)ix.p.dim * (ix.p.family == FLINNG_SRP_F32 ? 4 : 2)
+                                : nitems * (ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4);
+    b.offs = (vbytes + 7) & ~(size_t)7;
+    b.in_bytes = dense ? vbytes : b.offs + (nq + 1) * 8;
+    size_t o = 0;
+    b.in = o;
+    o += Arena::round(b.in_bytes);
+    b.codes = o;
+    o += Arena::round(nq * (size_t)ix.p.L * 4);
+    b.out = o;
+    o += Arena::round(2 * nq * (size_t)k * 4);
+    b.work = o;
+    o += Arena::round(4);
+    b.hash = o;
+    o += dense ? srp_scratch_bytes(ix, nq) : 0;
+    b.total = o;
     return b;
 }
+
+uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k) {
+    return plan_batch(ix, nq, nitems, k).total;
+}
+
+// Pinned host memory mapped into the device's address space, coherent, so
+// kernels read request payloads from it and write results into it directly.
+struct Pinned {
+    unsigned char *host = nullptr;
+    uint64_t dev = 0;  // the same memory as a device address
+};
+
+static bool pinned_alloc(size_t bytes, Pinned *out) {
+    void *h = nullptr;
+    if (hipHostMalloc(&h, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return false;
+    }
+    out->host = static_cast<unsigned char *>(h);
+    out->dev = reinterpret_cast<uint64_t>(d);
+    return true;
+}
+
+// Pinned blocks for large request payloads, reused from request to request
+// (size classes of 64 KiB * 2^c): a payload is copied once, at submit, into
+// memory the device reads directly, with no page faults once the pool is
+// warm.  At most `cap` bytes are pinned; beyond that payloads stay in the
+// heap and are packed like small ones.
+struct PinnedPool {
+    static constexpr size_t MIN = (size_t)64 << 10;
+    std::mutex mu;
+    std::vector<std::vector<Pinned>> free_;
+    size_t held = 0, cap = (size_t)1 << 30;
+    static int cls_of(size_t b) {
+        int c = 0;
+        while ((MIN << c) < b) ++c;
+        return c;
+    }
+    bool get(size_t bytes, Pinned *out, int *cls) {
+        const int c = cls_of(bytes);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if ((int)free_.size() > c && !free_[c].empty()) {
+                *out = free_[c].back();
+                free_[c].pop_back();
+                *cls = c;
+                return true;
+            }
+            if (held + (MIN << c) > cap) return false;
+            held += MIN << c;
+        }
+        if (!pinned_alloc(MIN << c, out)) {
+            std::lock_guard<std::mutex> lk(mu);
+            held -= MIN << c;
+            return false;
+        }
+        *cls = c;
+        return true;
+    }
+    void put(const Pinned &p, int c) {
+        std::lock_guard<std::mutex> lk(mu);
+        if ((int)free_.size() <= c) free_.resize(c + 1);
+        free_[c].push_back(p);
+    }
+    ~PinnedPool() {
+        for (auto &v : free_)
+            for (const Pinned &p : v) (void)hipHostFree(p.host);
+    }
+};
 
 struct Request {
     uint64_t ticket = 0;
     uint32_t slot = 0, k = 0;
     uint64_t nq = 0, nitems = 0;
-    std::vector<unsigned char> values;
+    size_t vbytes = 0;
+    std::vector<unsigned char> values;  // small payloads (or the pool is full)
+    Pinned pinned;                       // large payloads: a block of the pool
+    int pcls = -1;
+    PinnedPool *pool = nullptr;
     std::vector<uint64_t> offsets;  // rebased to 0 (sets)
     Clock::time_point t_submit, t_done;
     std::vector<uint32_t> ids, scores;
     int status = 0;
     bool done = false;
     uint64_t mem = 0;
+    void set_payload(const unsigned char *src, size_t n) {
+        vbytes = n;
+        if (n >= PinnedPool::MIN && pool && pool->get(n, &pinned, &pcls))
+            std::memcpy(pinned.host, src, n);
+        else
+            values.assign(src, src + n);
+    }
+    // the payload is not needed once the batch's input copy has completed
+    void release_payload() {
+        if (pinned.host) pool->put(pinned, pcls);
+        pinned = Pinned();
+        std::vector<unsigned char>().swap(values);
+        std::vector<uint64_t>().swap(offsets);
+    }
+    ~Request() { release_payload(); }
 };
 
-struct Lane {  // one stream and its in-flight batch
+struct Lane {  // one stream, its in-flight batch and its reusable buffers
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<Request *> reqs;
-    uint64_t nq = 0, mem = 0;
+    uint64_t nq = 0, nitems = 0;
     uint32_t k = 0;
-    unsigned char *hin = nullptr;
+    BatchPlan plan;
+    Pinned hin;                     // packed small payloads and offsets
     size_t hin_cap = 0;
-    uint32_t *hout = nullptr;
+    Pinned hout;                    // ids then scores of the batch
     size_t hout_cap = 0;
-    DevBuf din, doff, dcodes, dids, dsc, dwork;
+    std::vector<CopySeg> segs;
+    char *arena = nullptr;          // device workspace, kept between batches
+    size_t arena_cap = 0;
     int status = 0;
 };
 
 struct Server {
+    PinnedPool pool;
     std::vector<Index *> idx;
     flinng_serve_config cfg{};
     int device = 0;
@@ -83,7 +203,7 @@ struct Server {
     std::vector<Lane> lanes;
     std::thread sched;
     bool stop = false;
-    uint64_t next_ticket = 1, mem_inuse = 0;
+    uint64_t next_ticket = 1;
     // stats
     Clock::time_point t0;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, queries = 0;
@@ -91,82 +211,144 @@ struct Server {
     std::vector<double> lat_ms;
 };
 
-static void ensure_pinned(unsigned char **p, size_t *cap, size_t need) {
+// Device bytes held by all lane workspaces.
+static uint64_t held_bytes(const Server &S) {
+    uint64_t h = 0;
+    for (const Lane &ln : S.lanes) h += ln.arena_cap;
+    return h;
+}
+
+static void ensure_pinned(Pinned *p, size_t *cap, size_t need) {
     if (*cap >= need) return;
-    if (*p) (void)hipHostFree(*p);
-    *p = nullptr;
-    size_t c = std::max<size_t>(need, 1 << 16);
-    FL_HIP(hipHostMalloc(reinterpret_cast<void **>(p), c, hipHostMallocDefault));
+    const size_t c = std::max<size_t>({need, 2 * *cap, (size_t)1 << 20});
+    if (p->host) (void)hipHostFree(p->host);
+    *p = Pinned();
+    *cap = 0;
+    if (!pinned_alloc(c, p)) fail(FLINNG_ENOMEM, "pinned host allocation failed");
     *cap = c;
 }
 
-// Launch one batch on a lane (scheduler thread, without the lock).
+// Give lane ln a workspace of at least `need` bytes without letting the
+// workspaces of all lanes exceed the budget: the other busy lanes' holdings
+// are fixed, idle lanes give theirs back when room is needed.  The caller has
+// checked need <= budget - (other busy lanes' holdings).  Lock held.
+static void grow_arena(Server &S, Lane &ln, uint64_t need) {
+    if (ln.arena_cap >= need) return;
+    const uint64_t budget = S.cfg.mem_budget;
+    uint64_t busy_other = 0;
+    for (const Lane &o : S.lanes)
+        if (&o != &ln && o.busy) busy_other += o.arena_cap;
+    const uint64_t allowed = budget - busy_other;
+    uint64_t want = std::min<uint64_t>(std::max<uint64_t>(need, 2 * (uint64_t)ln.arena_cap), allowed);
+    if (held_bytes(S) - ln.arena_cap + want > budget) {
+        for (Lane &o : S.lanes)
+            if (&o != &ln && !o.busy && o.arena) {
+                (void)hipFreeAsync(o.arena, o.stream);
+                o.arena = nullptr;
+                o.arena_cap = 0;
+            }
+    }
+    if (ln.arena) (void)hipFreeAsync(ln.arena, ln.stream);
+    ln.arena = nullptr;
+    ln.arena_cap = 0;
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, want, ln.stream);
+    if (e != hipSuccess && want > need) {
+        (void)hipGetLastError();
+        want = need;
+        e = hipMallocAsync(&p, want, ln.stream);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FLINNG_ENOMEM, "serving workspace allocation failed");
+    }
+    ln.arena = static_cast<char *>(p);
+    ln.arena_cap = want;
+    S.peak_mem = std::max<uint64_t>(S.peak_mem, held_bytes(S));
+}
+
+// Launch one batch on a lane (scheduler thread, without the lock): pack the
+// requests into pinned memory, one copy in, hash + count + decode, one copy
+// out, then the completion event.
 static void launch(Server &S, Lane &ln) {
     const Index &ix = *S.idx[ln.reqs[0]->slot];
     const bool dense = is_dense(ix.p.family);
     const uint32_t k = ln.k;
-    uint64_t nq = 0, nitems = 0, vbytes = 0;
+    const uint64_t nq = ln.nq;
+    const BatchPlan &pl = ln.plan;
+    ensure_pinned(&ln.hin, &ln.hin_cap, pl.in_bytes + 16 * (ln.reqs.size() + 2));
+    hipStream_t s = ln.stream;
+    char *base = ln.arena;
+    const uint64_t dev_in = reinterpret_cast<uint64_t>(base + pl.in);
+    // one segment per pooled payload (read from its pinned block), one per
+    // run of small payloads packed into the lane's pinned buffer, and (sets)
+    // one for the offsets rebased to the batch; values stay in query order
+    ln.segs.clear();
+    size_t dst = 0, hpos = 0, run_dst = 0, run_src = 0, run_len = 0;
+    auto flush = [&] {
+        if (run_len) ln.segs.push_back({ln.hin.dev + run_src, dev_in + run_dst, run_len});
+        run_len = 0;
+    };
     for (Request *r : ln.reqs) {
-        nq += r->nq;
-        nitems += r->nitems;
-        vbytes += r->values.size();
+        if (r->pinned.host) {
+            flush();
+            ln.segs.push_back({r->pinned.dev, dev_in + dst, r->vbytes});
+        } else if (r->vbytes) {
+            if (!run_len) {
+                hpos = (hpos + 15) & ~(size_t)15;
+                run_dst = dst;
+                run_src = hpos;
+            }
+            std::memcpy(ln.hin.host + hpos, r->values.data(), r->vbytes);
+            hpos += r->vbytes;
+            run_len += r->vbytes;
+        }
+        dst += r->vbytes;
     }
-    ln.nq = nq;
-    const size_t obytes = dense ? 0 : (nq + 1) * 8;
-    ensure_pinned(&ln.hin, &ln.hin_cap, vbytes + obytes + 8);
-    // pack values, then rebased offsets
-    size_t vo = 0;
-    uint64_t *ho = reinterpret_cast<uint64_t *>(ln.hin + ((vbytes + 7) & ~(size_t)7));
-    uint64_t qi = 0, ibase = 0;
-    for (Request *r : ln.reqs) {
-        std::memcpy(ln.hin + vo, r->values.data(), r->values.size());
-        vo += r->values.size();
-        if (!dense) {
+    flush();
+    if (!dense) {
+        hpos = (hpos + 15) & ~(size_t)15;
+        uint64_t *ho = reinterpret_cast<uint64_t *>(ln.hin.host + hpos);
+        uint64_t qi = 0, ibase = 0;
+        for (Request *r : ln.reqs) {
             for (uint64_t i = 0; i < r->nq; ++i) ho[qi + i] = ibase + r->offsets[i];
             qi += r->nq;
             ibase += r->nitems;
         }
+        ho[nq] = ibase;
+        ln.segs.push_back({ln.hin.dev + hpos, dev_in + pl.offs, (nq + 1) * 8});
     }
-    if (!dense) ho[nq] = ibase;
-    hipStream_t s = ln.stream;
-    ln.din = DevBuf(std::max<size_t>(vbytes, 8), s);
-    FL_HIP(hipMemcpyAsync(ln.din.ptr, ln.hin, vbytes, hipMemcpyHostToDevice, s));
+    copy_segments(ln.segs.data(), ln.segs.size(), s);
     flinng_input in{};
-    in.values = ln.din.ptr;
+    in.values = base + pl.in;
     in.count = nq;
     in.on_device = 1;
-    if (!dense) {
-        ln.doff = DevBuf(obytes, s);
-        FL_HIP(hipMemcpyAsync(ln.doff.ptr, ho, obytes, hipMemcpyHostToDevice, s));
-        in.offsets = ln.doff.as<uint64_t>();
-    }
-    ln.dcodes = DevBuf(nq * ix.p.L * 4, s);
-    hash_batch(ix, in, ln.dcodes.as<uint32_t>(), s, nullptr,
-               dense ? -1.0 : (double)nitems / (double)nq);
-    ln.dids = DevBuf(nq * k * 4, s);
-    ln.dsc = DevBuf(nq * k * 4, s);
-    ln.dwork = DevBuf(S.cfg.persistent ? 4 : 0, s);
-    query_launch(ix, ln.dcodes.as<uint32_t>(), nq, k, ln.dids.as<uint32_t>(), ln.dsc.as<uint32_t>(),
-                 S.cfg.persistent != 0, s, ln.dwork.as<uint32_t>());
-    unsigned char *hout = reinterpret_cast<unsigned char *>(ln.hout);
-    ensure_pinned(&hout, &ln.hout_cap, 2 * nq * k * 4);
-    ln.hout = reinterpret_cast<uint32_t *>(hout);
-    FL_HIP(hipMemcpyAsync(ln.hout, ln.dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
-    FL_HIP(hipMemcpyAsync(ln.hout + nq * k, ln.dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
+    if (!dense) in.offsets = reinterpret_cast<const uint64_t *>(base + pl.in + pl.offs);
+    uint32_t *codes = reinterpret_cast<uint32_t *>(base + pl.codes);
+    uint32_t *out = reinterpret_cast<uint32_t *>(base + pl.out);
+    Arena ws{base + pl.hash, pl.total - pl.hash, 0};
+    hash_batch(ix, in, codes, s, nullptr, dense ? -1.0 : (double)ln.nitems / (double)nq, &ws);
+    query_launch(ix, codes, nq, k, out, out + nq * k, S.cfg.persistent != 0, s,
+                 reinterpret_cast<uint32_t *>(base + pl.work));
+    ensure_pinned(&ln.hout, &ln.hout_cap, 2 * nq * k * 4);
+    const CopySeg back{reinterpret_cast<uint64_t>(out), ln.hout.dev, 2 * nq * k * 4};
+    copy_segments(&back, 1, s);
     FL_HIP(hipEventRecord(ln.done, s));
 }
 
 // Finish a completed lane (scheduler thread, lock held).
 static void finish(Server &S, Lane &ln) {
     const auto now = Clock::now();
+    const uint32_t *ids = reinterpret_cast<const uint32_t *>(ln.hout.host);
+    const uint32_t *sc = ids + ln.nq * ln.k;
     uint64_t qi = 0;
     for (Request *r : ln.reqs) {
         if (ln.status == 0) {
-            r->ids.assign(ln.hout + qi * ln.k, ln.hout + (qi + r->nq) * ln.k);
-            r->scores.assign(ln.hout + ln.nq * ln.k + qi * ln.k,
-                             ln.hout + ln.nq * ln.k + (qi + r->nq) * ln.k);
+            r->ids.assign(ids + qi * ln.k, ids + (qi + r->nq) * ln.k);
+            r->scores.assign(sc + qi * ln.k, sc + (qi + r->nq) * ln.k);
         }
         qi += r->nq;
+        r->release_payload();
         r->status = ln.status;
         r->t_done = now;
         r->done = true;
@@ -174,15 +356,8 @@ static void finish(Server &S, Lane &ln) {
         S.completed++;
     }
     S.queries += ln.nq;
-    S.mem_inuse -= ln.mem;
     ln.reqs.clear();
     ln.busy = false;
-    ln.din.release();
-    ln.doff.release();
-    ln.dcodes.release();
-    ln.dids.release();
-    ln.dsc.release();
-    ln.dwork.release();
     S.cv_done.notify_all();
 }
 
@@ -209,6 +384,7 @@ static void scheduler(Server *Sp) {
         if (S.stop && !any_busy) break;
         // 2. admit and launch as many batches as free lanes and memory allow
         bool launched = false;
+        Clock::time_point wake = Clock::time_point::max();
         while (!S.stop && !S.queue.empty()) {
             Lane *free_lane = nullptr;
             for (Lane &ln : S.lanes)
@@ -217,8 +393,15 @@ static void scheduler(Server *Sp) {
                     break;
                 }
             if (!free_lane) break;
+            Lane &ln = *free_lane;
             Request *head = S.queue.front();
             const Index &ix = *S.idx[head->slot];
+            // device bytes this lane may hold while the other busy lanes keep theirs
+            uint64_t busy_other = 0;
+            for (const Lane &o : S.lanes)
+                if (&o != &ln && o.busy) busy_other += o.arena_cap;
+            const uint64_t allowed =
+                S.cfg.mem_budget > busy_other ? S.cfg.mem_budget - busy_other : 0;
             std::vector<Request *> take;
             uint64_t nq = 0, nitems = 0;
             for (auto it = S.queue.begin(); it != S.queue.end();) {
@@ -228,38 +411,54 @@ static void scheduler(Server *Sp) {
                     continue;
                 }
                 if (!take.empty() && nq + r->nq > S.cfg.max_batch) break;
-                const uint64_t need = batch_device_bytes(ix, nq + r->nq, nitems + r->nitems, head->k);
-                if (!take.empty() && S.mem_inuse + need > S.cfg.mem_budget) break;
+                if (!take.empty() &&
+                    batch_device_bytes(ix, nq + r->nq, nitems + r->nitems, head->k) > allowed)
+                    break;
                 take.push_back(r);
                 nq += r->nq;
                 nitems += r->nitems;
                 it = S.queue.erase(it);
             }
-            const uint64_t need = batch_device_bytes(ix, nq, nitems, head->k);
-            if (S.mem_inuse + need > S.cfg.mem_budget && S.mem_inuse > 0) {
+            const BatchPlan plan = plan_batch(ix, nq, nitems, head->k);
+            if (S.cfg.linger_ns && nq < S.cfg.max_batch) {
+                // not full: hold it until the oldest request has lingered long enough
+                const auto until = head->t_submit + std::chrono::nanoseconds(S.cfg.linger_ns);
+                if (Clock::now() < until) {
+                    for (auto it = take.rbegin(); it != take.rend(); ++it) S.queue.push_front(*it);
+                    wake = std::min(wake, until);
+                    break;
+                }
+            }
+            if (plan.total > allowed) {
                 // wait for memory: put the requests back in order
                 for (auto it = take.rbegin(); it != take.rend(); ++it) S.queue.push_front(*it);
                 break;
             }
-            Lane &ln = *free_lane;
             ln.reqs = take;
             ln.k = head->k;
-            ln.mem = need;
+            ln.nq = nq;
+            ln.nitems = nitems;
+            ln.plan = plan;
             ln.busy = true;
             ln.status = 0;
-            S.mem_inuse += need;
-            S.peak_mem = std::max(S.peak_mem, S.mem_inuse);
             S.batches++;
-            lk.unlock();
             int st = 0;
             try {
-                launch(S, ln);
+                grow_arena(S, ln, plan.total);
             } catch (const Error &e) {
                 st = e.code;
-            } catch (...) {
-                st = FLINNG_EDEVICE;
             }
-            lk.lock();
+            if (!st) {
+                lk.unlock();
+                try {
+                    launch(S, ln);
+                } catch (const Error &e) {
+                    st = e.code;
+                } catch (...) {
+                    st = FLINNG_EDEVICE;
+                }
+                lk.lock();
+            }
             if (st) {
                 ln.status = st;
                 (void)hipStreamSynchronize(ln.stream);
@@ -273,8 +472,26 @@ static void scheduler(Server *Sp) {
         for (Lane &ln : S.lanes) busy |= ln.busy;
         if (busy)
             S.cv_sched.wait_for(lk, std::chrono::microseconds(20));
+        else if (!S.stop && wake != Clock::time_point::max())
+            S.cv_sched.wait_until(lk, wake);
         else if (!S.stop)
             S.cv_sched.wait(lk);
+    }
+}
+
+// Release every lane's stream, event and buffers (no batch in flight).
+static void free_lanes(Server &S) {
+    for (Lane &ln : S.lanes) {
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+        if (ln.done) (void)hipEventDestroy(ln.done);
+        if (ln.hin.host) (void)hipHostFree(ln.hin.host);
+        if (ln.hout.host) (void)hipHostFree(ln.hout.host);
+        if (ln.arena) {
+            (void)hipFreeAsync(ln.arena, ln.stream);
+            (void)hipStreamSynchronize(ln.stream);
+        }
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        ln = Lane();
     }
 }
 
@@ -308,26 +525,41 @@ int flinng_serve_create(flinng_index *const *indexes, uint32_t n_idx, const flin
         if (cfg->max_inflight < 1 || cfg->max_inflight > 16) fail(FLINNG_EINVAL, "max_inflight must be in 1..16");
         if (cfg->max_batch < 1) fail(FLINNG_EINVAL, "max_batch must be >= 1");
         *out = nullptr;
-        Server *S = new Server();
+        std::unique_ptr<Server> S(new Server());
         S->cfg = *cfg;
         if (S->cfg.max_queue == 0) S->cfg.max_queue = 1u << 20;
         for (uint32_t i = 0; i < n_idx; ++i) {
-            if (!indexes[i]) {
-                delete S;
-                fail(FLINNG_EINVAL, "NULL index");
-            }
+            if (!indexes[i]) fail(FLINNG_EINVAL, "NULL index");
             S->idx.push_back(reinterpret_cast<Index *>(indexes[i]));
         }
         S->device = S->idx[0]->device;
-        (void)hipSetDevice(S->device);
+        FL_HIP(hipSetDevice(S->device));
         S->lanes.resize(cfg->max_inflight);
-        for (Lane &ln : S->lanes) {
-            FL_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
-            FL_HIP(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+        try {
+            for (Lane &ln : S->lanes) {
+                FL_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
+                FL_HIP(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+                // pinned buffers of a typical batch, and one round trip through
+                // the copy kernel on each stream, so the first requests do not
+                // pay for setting them up
+                ensure_pinned(&ln.hin, &ln.hin_cap, 1 << 20);
+                ensure_pinned(&ln.hout, &ln.hout_cap, 1 << 20);
+                std::memset(ln.hin.host, 0, 4096);
+                DevBuf probe(4096, ln.stream);
+                const uint64_t pd = reinterpret_cast<uint64_t>(probe.ptr);
+                const CopySeg in{ln.hin.dev, pd, 4096}, out{pd, ln.hout.dev, 4096};
+                copy_segments(&in, 1, ln.stream);
+                copy_segments(&out, 1, ln.stream);
+                probe.release();
+                FL_HIP(hipStreamSynchronize(ln.stream));
+            }
+        } catch (...) {
+            free_lanes(*S);
+            throw;
         }
         S->t0 = Clock::now();
-        S->sched = std::thread(scheduler, S);
-        *out = reinterpret_cast<flinng_server *>(S);
+        S->sched = std::thread(scheduler, S.get());
+        *out = reinterpret_cast<flinng_server *>(S.release());
     });
 }
 
@@ -342,6 +574,7 @@ int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_inpu
         if (q->on_device) fail(FLINNG_EINVAL, "serving takes host inputs");
         const Index &ix = *S.idx[idx_slot];
         Request *r = new Request();
+        r->pool = &S.pool;
         r->slot = idx_slot;
         r->k = k;
         r->nq = q->count;
@@ -352,8 +585,7 @@ int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_inpu
             }
             const size_t esz = ix.p.family == FLINNG_SRP_F32 ? 4 : 2;
             const size_t bytes = q->count * ix.p.dim * esz;
-            r->values.assign(static_cast<const unsigned char *>(q->values),
-                             static_cast<const unsigned char *>(q->values) + bytes);
+            r->set_payload(static_cast<const unsigned char *>(q->values), bytes);
         } else {
             if (!q->offsets) {
                 delete r;
@@ -371,7 +603,7 @@ int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_inpu
             }
             r->nitems = last - first;
             const unsigned char *v = static_cast<const unsigned char *>(q->values) + first * isz;
-            r->values.assign(v, v + r->nitems * isz);
+            r->set_payload(v, r->nitems * isz);
         }
         r->mem = batch_device_bytes(ix, r->nq, r->nitems, k);
         std::lock_guard<std::mutex> lk(S.mu);
@@ -462,6 +694,18 @@ int flinng_serve_stats_get(flinng_server *srv, flinng_serve_stats *st) {
     });
 }
 
+int flinng_serve_stats_reset(flinng_server *srv) {
+    return sguard([&] {
+        if (!srv) fail(FLINNG_EINVAL, "NULL argument");
+        Server &S = *reinterpret_cast<Server *>(srv);
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.submitted = S.completed = S.rejected = S.batches = S.queries = 0;
+        S.lat_ms.clear();
+        S.peak_mem = held_bytes(S);
+        S.t0 = Clock::now();
+    });
+}
+
 void flinng_serve_destroy(flinng_server *srv) {
     if (!srv) return;
     Server *S = reinterpret_cast<Server *>(srv);
@@ -477,19 +721,7 @@ void flinng_serve_destroy(flinng_server *srv) {
     S->cv_sched.notify_all();
     if (S->sched.joinable()) S->sched.join();
     for (auto &kv : S->tickets) delete kv.second;
-    for (Lane &ln : S->lanes) {
-        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
-        if (ln.done) (void)hipEventDestroy(ln.done);
-        if (ln.hin) (void)hipHostFree(ln.hin);
-        if (ln.hout) (void)hipHostFree(ln.hout);
-        ln.din.release();
-        ln.doff.release();
-        ln.dcodes.release();
-        ln.dids.release();
-        ln.dsc.release();
-        ln.dwork.release();
-        if (ln.stream) (void)hipStreamDestroy(ln.stream);
-    }
+    free_lanes(*S);
     delete S;
 }
 

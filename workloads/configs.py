@@ -14,9 +14,12 @@ CONFIGS = {
     "c1": dict(name="dense_gmm_10k_d128", family=SRP_F32, N=10_000, d=128,
                n_centres=100, K=8, L=4, R=3, B=100, bucket_bits=8, k=10,
                nq=100),
+    # tuned: the fastest (K, L) of a sweep at this R, B whose R1@10 on 3000
+    # queries clears 0.9 by more than two standard errors (K=1, L=8 reaches
+    # 0.904, within one; the configured K=2, L=32 reaches 0.79)
     "c2": dict(name="genome_reads_1M_minhash", family=MINHASH_U64,
                n_base=500_000, N=1_000_000, K=2, L=32, R=4, B=4096,
-               bucket_bits=20, k=10, nq=10_000),
+               bucket_bits=20, k=10, nq=10_000, tuned=dict(K=1, L=12)),
     "c3": dict(name="relu_embed_1M_d4096_bf16", family=SRP_BF16, N=1_000_000,
                d=4096, n_centres=10_000, K=16, L=64, R=8, B=8192,
                bucket_bits=16, k=10, nq=10_000),

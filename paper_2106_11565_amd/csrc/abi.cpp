@@ -185,7 +185,7 @@ int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
             build_groups(*ix, s);
             build_lists(*ix, codes.as<uint32_t>(), s);
             FL_HIP(hipStreamSynchronize(s));
-            bytes += ix->list_entries * ix->cell_bytes;
+            bytes += cells_alloc_bytes(ix->list_entries, ix->cell_bytes);
             ix->device_bytes = bytes;
         } catch (...) {
             free_index(ix);

@@ -211,10 +211,14 @@ void build_lists(Index &ix, const uint32_t *codes, hipStream_t s) {
             FL_CHECK_LAUNCH();
             base += nt;
         }
-        // shrink the list buffer to its exact size
+        // shrink the list buffer to its size plus a zeroed tail, so that the
+        // query kernel's 16-byte chunk reads past a list's end stay inside it
         void *exact = nullptr;
-        FL_HIP(hipMalloc(&exact, std::max<uint64_t>(base, 1) * csz));
-        if (base) FL_HIP(hipMemcpyAsync(exact, big, base * csz, hipMemcpyDeviceToDevice, s));
+        const size_t used = (size_t)base * csz;
+        FL_HIP(hipMalloc(&exact, cells_alloc_bytes(base, csz)));
+        if (base) FL_HIP(hipMemcpyAsync(exact, big, used, hipMemcpyDeviceToDevice, s));
+        FL_HIP(hipMemsetAsync(static_cast<char *>(exact) + used, 0,
+                              cells_alloc_bytes(base, csz) - used, s));
         FL_HIP(hipStreamSynchronize(s));
         FL_HIP(hipFree(big));
         big = nullptr;

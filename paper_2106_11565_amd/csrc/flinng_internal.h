@@ -85,6 +85,12 @@ struct Index {
 };
 
 inline uint64_t nbuckets(const Index &ix) { return 1ull << ix.nbits; }
+// Bytes allocated for n list entries of csz bytes: rounded up to 16 bytes
+// plus 16 more (zeroed), so aligned 16-byte reads covering any entry are in
+// bounds.
+inline size_t cells_alloc_bytes(uint64_t n, size_t csz) {
+    return ((n * csz + 15) & ~(size_t)15) + 16;
+}
 inline bool is_dense(uint32_t fam) { return fam == FLINNG_SRP_F32 || fam == FLINNG_SRP_BF16; }
 
 // Device scratch allocated on a stream (stream-ordered allocator).

@@ -33,11 +33,11 @@ namespace flinng {
 
 // Threads per query workgroup: 256, or 1024 when the per-query LDS state
 // leaves room for only one workgroup per CU (more wavefronts to hide
-// latency).  Histogram copies: one per wavefront up to HCMAX.
-constexpr int HCMAX = 4;
-__host__ __device__ constexpr int hist_copies(int T) {
-    return (T / 64) < HCMAX ? (T / 64) : (T >= 1024 ? 2 : HCMAX);
-}
+// latency).  The count histograms have HC copies (thread t adds to copy
+// t mod HC) so that the many increments of the few low count values do not
+// serialise on one LDS address; HC is a power of two sized to the LDS left
+// over.
+constexpr uint32_t HC_MAX = 32;
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
 constexpr uint32_t CL = 1024;      // positive-cell list capacity
 
@@ -52,6 +52,7 @@ struct QArgs {
     uint32_t L, R, Rp, B, Bp, nbits, k, cap;
     uint32_t mstride;      // member slots per cell (multiple of 4)
     uint32_t threads;      // workgroup size the kernel is launched with
+    uint32_t hc;           // histogram copies (a power of two)
     uint32_t *ids;
     uint32_t *scores;
     uint8_t *counts_out;   // debug: write counters and skip decode
@@ -65,24 +66,25 @@ struct QArgs {
 
 struct QLayout {
     uint32_t cnt_words, hist_words, cap;
-    size_t off_cnt, off_hist, off_pre, off_start, off_buf, off_lb, off_lp, off_misc, total;
+    size_t off_cnt, off_hist, off_pre, off_start, off_end, off_buf, off_lb, off_lp, off_misc, total;
 };
 
 __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp, uint32_t cap,
-                                            int T) {
+                                            int T, uint32_t hc) {
     QLayout l;
     l.cnt_words = (R * Bp) / 4;
-    l.hist_words = hist_copies(T) * R * (L + 1);
+    l.hist_words = hc * R * (L + 1);
     l.cap = cap;
     size_t o = 0;
     l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned first
     l.off_cnt = o;   o += (size_t)l.cnt_words * 4;
-    l.off_hist = o;  o += (size_t)l.hist_words * 4;
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
+    l.off_end = o;   o += (size_t)L * 4;
     l.off_lb = o;    o += CL * 4;
     l.off_lp = o;    o += (size_t)T * 4;
     l.off_misc = o;  o += 64 * 4;
+    l.off_hist = o;  o += (size_t)l.hist_words * 4;  // last: only its size varies with hc
     l.total = (o + 15) & ~(size_t)15;
     return l;
 }
@@ -283,15 +285,16 @@ __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t B
 template <typename CellT, int RP, int QT>
 __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
     constexpr int QW = QT / 64;
-    constexpr int HC = hist_copies(QT);
     extern __shared__ __align__(16) unsigned char lds[];
-    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap, QT);
+    const uint32_t HC = A.hc;
+    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap, QT, HC);
     uint64_t *buf = reinterpret_cast<uint64_t *>(lds + lay.off_buf);
     uint32_t *cnt32 = reinterpret_cast<uint32_t *>(lds + lay.off_cnt);
     const uint8_t *cnt8 = lds + lay.off_cnt;
     uint32_t *hist = reinterpret_cast<uint32_t *>(lds + lay.off_hist);
     uint32_t *pre = reinterpret_cast<uint32_t *>(lds + lay.off_pre);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(lds + lay.off_start);
+    uint32_t *lend = reinterpret_cast<uint32_t *>(lds + lay.off_end);
     uint32_t *lb = reinterpret_cast<uint32_t *>(lds + lay.off_lb);
     uint32_t *lp = reinterpret_cast<uint32_t *>(lds + lay.off_lp);
     uint32_t *misc = reinterpret_cast<uint32_t *>(lds + lay.off_misc);
@@ -316,33 +319,36 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         }
         if (q >= A.nq) break;
 
-        // ---- 1. zero counters and histograms
-        for (uint32_t w = tid; w < lay.cnt_words; w += QT) cnt32[w] = 0u;
-        for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
-
-        // ---- 2. list ranges of the query's L buckets
-        uint32_t len = 0, st = 0;
+        // ---- 1. the query's L list ranges (loads issued first, so that they
+        // are in flight while the counters are cleared), as 16-byte chunks
+        constexpr uint32_t CE = 16 / sizeof(CellT);  // list entries per chunk
+        uint32_t nch = 0, st = 0, en = 0;
         if ((uint32_t)tid < L) {
             const uint32_t h = A.codes[q * L + tid];
             const uint32_t *o = A.offsets + (uint64_t)tid * nbk1 + h;
             st = o[0];
-            len = o[1] - st;
+            en = o[1];
         }
-        uint32_t total;
-        uint32_t ex = wg_excl_scan<QT>(len, scr, &total);
+        for (uint32_t w = tid; w < lay.cnt_words; w += QT) cnt32[w] = 0u;
+        for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
+        if (en > st) nch = (en + CE - 1) / CE - st / CE;
+        uint32_t total;  // chunks over all tables
+        const uint32_t ex = wg_excl_scan<QT>(nch, scr, &total);
         if ((uint32_t)tid < L) {
             pre[tid] = ex;
             lstart[tid] = st;
+            lend[tid] = en;
         }
         if (tid == 0) pre[L] = total;
         __syncthreads();
 
-        // ---- 3. count: one increment per listed cell per table.  The
-        // flattened entry index idx belongs to the last table t with
-        // pre[t] <= idx; a thread's indices only grow, so after one binary
-        // search its table index only moves forward.  Four entries per thread
-        // are loaded before their LDS increments.
+        // ---- 2. count: one increment per listed cell per table.  Chunk ci
+        // belongs to the last table t with pre[t] <= ci; a thread's chunks
+        // only grow, so after one binary search its table index only moves
+        // forward.  Four aligned 16-byte chunks per thread are loaded before
+        // their increments; entries outside the table's list are skipped.
         {
+            const uint4 *cells16 = static_cast<const uint4 *>(A.cells);
             uint32_t t = 0;
             {
                 uint32_t lo = 0, hi = L;
@@ -354,21 +360,34 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
                 t = lo;
             }
             for (uint32_t base = tid; base < total; base += 4 * QT) {
-                uint32_t c4[4];
-                bool ok[4];
+                uint4 v[4];
+                uint32_t chunk[4], tt[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t idx = base + (uint32_t)u * QT;
-                    ok[u] = idx < total;
-                    c4[u] = 0;
-                    if (ok[u]) {
-                        while (t + 1 < L && pre[t + 1] <= idx) ++t;
-                        c4[u] = (uint32_t)cells[lstart[t] + (idx - pre[t])];
+                    const uint32_t ci = base + (uint32_t)u * QT;
+                    tt[u] = 0xFFFFFFFFu;
+                    chunk[u] = 0;
+                    v[u] = make_uint4(0, 0, 0, 0);
+                    if (ci < total) {
+                        while (t + 1 < L && pre[t + 1] <= ci) ++t;
+                        tt[u] = t;
+                        chunk[u] = lstart[t] / CE + (ci - pre[t]);
+                        v[u] = cells16[chunk[u]];
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (ok[u]) atomicAdd(&cnt32[c4[u] >> 2], 1u << (8 * (c4[u] & 3)));
+                for (int u = 0; u < 4; ++u) {
+                    if (tt[u] == 0xFFFFFFFFu) continue;
+                    const uint32_t lo = lstart[tt[u]], hi = lend[tt[u]];
+                    const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                    for (uint32_t e = 0; e < CE; ++e) {
+                        const uint32_t j = chunk[u] * CE + e;
+                        const uint32_t c = (CE == 8) ? ((w4[e / 2] >> (16 * (e & 1))) & 0xFFFFu)
+                                                     : w4[e % 4];
+                        if (j >= lo && j < hi) atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
+                    }
+                }
             }
         }
         __syncthreads();
@@ -382,16 +401,16 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             continue;
         }
 
-        // ---- 4. per-repetition histograms of nonzero counts (per-wave copies)
+        // ---- 3. per-repetition histograms of nonzero counts
         {
-            uint32_t *hw = hist + (wave % HC) * R * (L + 1);
+            uint32_t *hw = hist + ((uint32_t)tid & (HC - 1)) * R * (L + 1);
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
-                uint32_t v = cnt32[w];
+                const uint32_t v = cnt32[w];
                 if (!v) continue;
                 const uint32_t r = (4 * w) / Bp;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    uint32_t cv = (v >> (8 * j)) & 255u;
+                    const uint32_t cv = (v >> (8 * j)) & 255u;
                     if (cv) atomicAdd(&hw[r * (L + 1) + cv], 1u);
                 }
             }
@@ -399,8 +418,15 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         __syncthreads();
         for (uint32_t i = tid; i < R * (L + 1); i += QT) {
             uint32_t sacc = 0;
+            // constant trip counts: a loop bounded by HC alone costs registers
+            if (HC <= 4) {
 #pragma unroll
-            for (int w = 0; w < HC; ++w) sacc += hist[w * R * (L + 1) + i];
+                for (uint32_t w = 0; w < 4; ++w)
+                    if (w < HC) sacc += hist[w * R * (L + 1) + i];
+            } else {
+                for (uint32_t w = 0; w < HC_MAX; ++w)
+                    if (w < HC) sacc += hist[w * R * (L + 1) + i];
+            }
             hist[i] = sacc;
         }
         __syncthreads();
@@ -476,7 +502,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         }
         __syncthreads();
 
-        // ---- 5. decode passes
+        // ---- 4. decode passes
         unsigned long long st_all = 0, st_final = 0, st_passes = 0;  // tid 0 only
         for (;;) {
             if (tid == 0) {
@@ -740,7 +766,9 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             if (misc[M_DONE]) break;
         }
         if (A.stats && tid == 0) {
-            atomicAdd(&A.stats[0], (unsigned long long)total);
+            unsigned long long entries = 0;
+            for (uint32_t t = 0; t < L; ++t) entries += lend[t] - lstart[t];
+            atomicAdd(&A.stats[0], entries);
             atomicAdd(&A.stats[1], st_all);
             atomicAdd(&A.stats[2], st_final);
             atomicAdd(&A.stats[3], st_passes);
@@ -765,19 +793,41 @@ static uint32_t cap_for(uint32_t k, int T) {
 
 static int max_lds();
 
-// 1024 threads when a 256-thread workgroup's state already fills more than
-// half of the LDS (one workgroup per CU either way), else 256.
-static int threads_for(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
-    const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256).total;
-    if (small * 2 <= (size_t)max_lds()) return 256;
-    const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024).total;
-    return big <= (size_t)max_lds() ? 1024 : 256;
+// Launch shape of the query kernel for one index and k.
+struct QShape {
+    int T;
+    uint32_t cap, hc;
+    size_t lds;
+};
+
+// 256 threads when four such workgroups fit in a CU's LDS (the register
+// budget admits four per CU: 16 wavefronts), else 1024 threads with one
+// workgroup per CU (also 16).  The histogram copies take what the LDS share
+// of one workgroup has left, up to HC_MAX.
+static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
+    const size_t lim = (size_t)max_lds();
+    const size_t bins = (size_t)R * (L + 1) * 4;
+    QShape sh;
+    const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256, 1).total;
+    if (small * 4 <= lim) {
+        // a state this small holds few cells, so few counts collide: four
+        // copies (more only add clearing and merging)
+        sh.T = 256;
+        sh.hc = (uint32_t)std::min<size_t>(4, 1 + (lim / 4 - small) / bins);
+    } else {
+        const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024, 1).total;
+        sh.T = big <= lim ? 1024 : 256;
+        sh.hc = big <= lim ? (uint32_t)std::min<size_t>(HC_MAX, 1 + (lim - big) / bins) : 1u;
+    }
+    while (sh.hc & (sh.hc - 1)) sh.hc &= sh.hc - 1;  // round down to a power of two
+    sh.cap = cap_for(k, sh.T);
+    sh.lds = q_layout(L, R, Bp, sh.cap, sh.T, sh.hc).total;
+    return sh;
 }
 
 size_t query_lds_bytes(const Index &ix, uint32_t k) {
     const uint32_t Bp = (ix.p.B + 3) & ~3u;
-    const int T = threads_for(ix.p.L, ix.p.R, Bp, k);
-    return q_layout(ix.p.L, ix.p.R, Bp, cap_for(k, T), T).total;
+    return q_shape(ix.p.L, ix.p.R, Bp, k).lds;
 }
 
 static int max_lds() {
@@ -861,8 +911,10 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.Bp = (ix.p.B + 3) & ~3u;
     a.nbits = ix.nbits;
     a.k = k;
-    a.threads = threads_for(a.L, a.R, a.Bp, k);
-    a.cap = cap_for(k, (int)a.threads);
+    const QShape sh = q_shape(a.L, a.R, a.Bp, k);
+    a.threads = (uint32_t)sh.T;
+    a.cap = sh.cap;
+    a.hc = sh.hc;
     a.mstride = ix.mstride;
     a.budget = BUDGET;
     return a;
@@ -877,7 +929,7 @@ void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint3
     a.scores = scores_dev;
     a.work = persistent ? work_counter : nullptr;
     a.stats = stats;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc).total;
     if ((int)lds > max_lds())
         fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +
                                 " bytes) exceeds the workgroup LDS limit; reduce B*R or k");
@@ -893,7 +945,7 @@ void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint
     if (nq == 0) return;
     QArgs a = make_args(ix, codes_dev, nq, 1);
     a.counts_out = counts_dev;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc).total;
     if ((int)lds > max_lds()) fail(FLINNG_EINVAL, "per-query state exceeds the LDS limit");
     if (ix.cell_bytes == 2)
         launch_q<uint16_t>(a, lds, false, s);

@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
 
 
 def log(*a):
@@ -51,6 +52,9 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device three times (a plain copy of known "
+                         "size, for scaling the HBM byte counters of a profiled run)")
     ap.add_argument("--fixed", action="store_true",
                     help="use the workload's configured (K, L) even where a tuned setting exists")
     ap.add_argument("--pareto", action="store_true",
@@ -192,7 +196,8 @@ def stages(w, torch, fl, steps, persistent, out):
     alg = w.nq * w.L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * w.R + w.nq * w.k * 8
     ach = alg / (decode_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": "query_kernel (count + threshold + decode)",
             "alg_bytes_per_launch": int(alg), "launch_ms": round(decode_ms, 4),
             "list_entries": st[0], "member_ids_all_passes": st[1], "member_ids_final": st[2],
@@ -200,6 +205,24 @@ def stages(w, torch, fl, steps, persistent, out):
     log(f"hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg / 1e6:.1f} MB -> "
         f"{ach:.0f} GB/s; stats {st}")
     return hash_ms, decode_ms, roof
+
+
+def measured_traffic(w):
+    """HBM bytes per query_kernel launch from the committed counter summary
+    (two rocprofv3 --pmc passes, scaled by a plain copy of known size), if
+    it was taken for this workload and (K, L) with the current kernel
+    source; None otherwise."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2106_11565_amd", "csrc", "query.hip")
+    path = os.path.join(ROOT, "profiles", "traffic_query_kernel.md")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cols) >= 9 and cols[0] == w.cfg["name"] and cols[1] == str(w.K) and cols[2] == str(w.L):
+            return int(cols[8]) if cols[3] == sha else None
+    return None
 
 
 def recall(w, fl, ids, nq_sample):
@@ -251,13 +274,16 @@ def poisson_requests(workloads, n_req, seed, sizes=None):
     return out
 
 
-def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False):
+def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False, submitters=1):
     """Submit `reqs` to a fresh server (after a warm-up burst of the first 64),
     open loop: exponential inter-arrival gaps with mean (mean request size /
-    rate_qps), or all at once when rate_qps is 0.  A second thread waits for the tickets in order.  Returns
-    the achieved rate (queries / time from first submit to last completion),
-    the server's latency percentiles (completion - submit) and whether every
-    result equals the plain batched result for the same queries."""
+    rate_qps), or all at once when rate_qps is 0.  `submitters` client
+    threads share the arrivals round-robin (the library copies a request's
+    payload inside the submit call, outside the Python lock, so they copy in
+    parallel); one more thread waits for the tickets.  Returns the achieved
+    rate (queries / time from first arrival to last completion), the server's
+    latency percentiles (completion - submit) and whether every result equals
+    the plain batched result for the same queries."""
     import numpy as np
     rng = np.random.default_rng(seed)
     mean = float(np.mean([r[2] for r in reqs]))
@@ -265,14 +291,15 @@ def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False):
                 else np.zeros(len(reqs)))
     srv = fl.Server([w.index for w in workloads], mem_budget=8 << 30, max_inflight=4,
                     max_batch=4096, persistent=persistent)
-    # warm-up: one burst sizes every stream's workspace; statistics restart
-    # after it so that they describe the steady state
+    # warm-up: one burst sizes every stream's workspace and the payload pool;
+    # statistics restart after it so that they describe the steady state
     warm = [srv.submit(r[0], r[1], workloads[r[0]].k) + (workloads[r[0]].k,) for r in reqs[:64]]
     for tk, n, k in warm:
         srv.wait(tk, n, k)
     srv.reset_stats()
     tq = queue.Queue()
-    state = {"same": True, "t_last": 0.0, "err": None}
+    state = {"same": True, "t_last": 0.0, "err": None, "lag": 0.0}
+    lock = threading.Lock()
 
     def waiter():
         try:
@@ -289,25 +316,36 @@ def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False):
         except Exception as e:  # surfaced after join
             state["err"] = e
 
+    def submitter(j, t0):
+        try:
+            lag = 0.0
+            for i in range(j, len(reqs), submitters):
+                r = reqs[i]
+                target = t0 + arrivals[i]
+                now = time.perf_counter()
+                while now < target:
+                    if target - now > 0.002:
+                        time.sleep(target - now - 0.001)
+                    now = time.perf_counter()
+                lag = max(lag, now - target)
+                k = workloads[r[0]].k
+                tk, n = srv.submit(r[0], r[1], k)
+                tq.put((tk, n, k, r))
+            with lock:
+                state["lag"] = max(state["lag"], lag)
+        except Exception as e:
+            state["err"] = e
+
     th = threading.Thread(target=waiter)
     th.start()
-    lag = 0.0
-    try:
-        t0 = time.perf_counter()
-        for i, r in enumerate(reqs):
-            target = t0 + arrivals[i]
-            now = time.perf_counter()
-            while now < target:
-                if target - now > 0.002:
-                    time.sleep(target - now - 0.001)
-                now = time.perf_counter()
-            lag = max(lag, now - target)
-            k = workloads[r[0]].k
-            tk, n = srv.submit(r[0], r[1], k)
-            tq.put((tk, n, k, r))
-    finally:
-        tq.put(None)
-        th.join()
+    t0 = time.perf_counter() + 0.01
+    subs = [threading.Thread(target=submitter, args=(j, t0)) for j in range(submitters)]
+    for t in subs:
+        t.start()
+    for t in subs:
+        t.join()
+    tq.put(None)
+    th.join()
     if state["err"] is not None:
         raise state["err"]
     wall = state["t_last"] - t0
@@ -318,7 +356,8 @@ def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False):
             "achieved_qps": round(nq / wall, 1), "p50_ms": round(st["p50_ms"], 3),
             "p99_ms": round(st["p99_ms"], 3), "requests": len(reqs), "queries": nq,
             "batches": st["batches"], "mean_batch": round(st["mean_batch"], 1),
-            "max_submit_lag_ms": round(lag * 1e3, 3), "identical_to_plain": bool(state["same"])}
+            "max_submit_lag_ms": round(state["lag"] * 1e3, 3), "submitters": submitters,
+            "identical_to_plain": bool(state["same"])}
 
 
 def cpu_baseline(w, ids, sc, seconds):
@@ -365,6 +404,14 @@ def main():
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     torch.cuda.init()
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {COPY_BYTES} bytes x 3")
+        del src, dst
     if args.workload == "c5":
         return main_mixed(args, torch, fl, configs)
     if args.pareto:

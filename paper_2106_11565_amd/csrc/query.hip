@@ -91,7 +91,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 
 // misc slots
 enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
-       M_THRHI, M_LCNT, M_MEMB, M_THI, M_SCAN0 };
+       M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_SCAN0 };
 
 template <int T>
 __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *total) {
@@ -282,8 +282,11 @@ __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t B
     }
 }
 
-template <typename CellT, int RP, int QT>
-__global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
+// GK: the general-k decode (k > 64) instead of the per-wavefront register
+// top-k; compiled separately so that the common path carries only its own
+// code (and registers).
+template <typename CellT, int RP, int QT, bool GK>
+__global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A) {
     constexpr int QW = QT / 64;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t HC = A.hc;
@@ -503,7 +506,13 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
         __syncthreads();
 
         // ---- 4. decode passes
-        unsigned long long st_all = 0, st_final = 0, st_passes = 0;  // tid 0 only
+        // per-query work tallies (members read, in the final pass, passes) in
+        // LDS rather than registers: they live across the whole decode
+        if (tid == 0) {
+            misc[M_ST_ALL] = 0;
+            misc[M_ST_FINAL] = 0;
+            misc[M_ST_PASSES] = 0;
+        }
         for (;;) {
             if (tid == 0) {
                 uint32_t level = misc[M_LEVEL];
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             const uint32_t *memr = A.mem + rep * rstride;
             const uint16_t *cmgr = A.cmg + rep * rstride * RP;
 
-          if (k <= 64) {
+          if constexpr (!GK) {
             // Fast decode (k <= 64): the positive cells of `rep` go into an
             // LDS list (one word-wide scan, or 256 cells at a time when they
             // do not fit); each wavefront streams (cell, 256-member chunk)
@@ -703,9 +712,11 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
           }
             const uint32_t nge = misc[M_NGE], nall = misc[M_NALL];
             const bool ok = nge >= k;
-            st_all += misc[M_MEMB];
-            st_passes += 1;
-            if (ok || keep) st_final = misc[M_MEMB];
+            if (tid == 0) {
+                misc[M_ST_ALL] += misc[M_MEMB];
+                misc[M_ST_PASSES] += 1;
+                if (ok || keep) misc[M_ST_FINAL] = misc[M_MEMB];
+            }
             if (ok || keep) {
                 // emit the buffered keys (and, for the fill path, zero cells)
                 const uint32_t nres = (nall < k ? nall : k);
@@ -769,10 +780,10 @@ __global__ __launch_bounds__(QT) void query_kernel(QArgs A) {
             unsigned long long entries = 0;
             for (uint32_t t = 0; t < L; ++t) entries += lend[t] - lstart[t];
             atomicAdd(&A.stats[0], entries);
-            atomicAdd(&A.stats[1], st_all);
-            atomicAdd(&A.stats[2], st_final);
-            atomicAdd(&A.stats[3], st_passes);
-            atomicAdd(&A.stats[4], st_final);
+            atomicAdd(&A.stats[1], (unsigned long long)misc[M_ST_ALL]);
+            atomicAdd(&A.stats[2], (unsigned long long)misc[M_ST_FINAL]);
+            atomicAdd(&A.stats[3], (unsigned long long)misc[M_ST_PASSES]);
+            atomicAdd(&A.stats[4], (unsigned long long)misc[M_ST_FINAL]);
         }
         __syncthreads();
         if (!A.work) break;
@@ -856,11 +867,11 @@ static int num_cus() {
     return v;
 }
 
-template <typename CellT, int RP, int QT>
+template <typename CellT, int RP, int QT, bool GK>
 static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
         attr_set = true;
     }
@@ -872,27 +883,31 @@ static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s
     }
     if (grid == 0) return;
     if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
-    hipLaunchKernelGGL((query_kernel<CellT, RP, QT>), dim3((unsigned)grid), dim3(QT), lds, s, a);
+    hipLaunchKernelGGL((query_kernel<CellT, RP, QT, GK>), dim3((unsigned)grid), dim3(QT), lds, s, a);
     FL_CHECK_LAUNCH();
 }
 
-template <typename CellT, int QT>
+template <typename CellT, int QT, bool GK>
 static void launch_t(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
     switch (a.Rp) {
-        case 1: launch_rp<CellT, 1, QT>(a, lds, persistent, s); break;
-        case 2: launch_rp<CellT, 2, QT>(a, lds, persistent, s); break;
-        case 4: launch_rp<CellT, 4, QT>(a, lds, persistent, s); break;
-        case 8: launch_rp<CellT, 8, QT>(a, lds, persistent, s); break;
-        default: launch_rp<CellT, 16, QT>(a, lds, persistent, s); break;
+        case 1: launch_rp<CellT, 1, QT, GK>(a, lds, persistent, s); break;
+        case 2: launch_rp<CellT, 2, QT, GK>(a, lds, persistent, s); break;
+        case 4: launch_rp<CellT, 4, QT, GK>(a, lds, persistent, s); break;
+        case 8: launch_rp<CellT, 8, QT, GK>(a, lds, persistent, s); break;
+        default: launch_rp<CellT, 16, QT, GK>(a, lds, persistent, s); break;
     }
 }
 
 template <typename CellT>
 static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
-    if (a.threads == 1024)
-        launch_t<CellT, 1024>(a, lds, persistent, s);
-    else
-        launch_t<CellT, 256>(a, lds, persistent, s);
+    const bool gk = a.k > 64;
+    if (a.threads == 1024) {
+        if (gk) launch_t<CellT, 1024, true>(a, lds, persistent, s);
+        else launch_t<CellT, 1024, false>(a, lds, persistent, s);
+    } else {
+        if (gk) launch_t<CellT, 256, true>(a, lds, persistent, s);
+        else launch_t<CellT, 256, false>(a, lds, persistent, s);
+    }
 }
 
 static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint32_t k) {

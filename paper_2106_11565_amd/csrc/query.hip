@@ -155,21 +155,42 @@ struct WaveState {
     uint32_t n_ge, n_all, members;
 };
 
-// Insert the keys flagged in `cand` into the wavefront's sorted top-k list.
+// Broadcast a 64-bit value from one lane (src uniform across the wavefront).
+__device__ inline uint64_t bcast64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Insert the keys flagged in `cand` into the wavefront's sorted top-k list,
+// all at once.  Each candidate below the k-th key is broadcast in turn
+// (readlane) and its place in the merged order found by ballot (its rank
+// among the list plus its rank among the candidates); every output position
+// notes which candidate lands on it and how many land before it.  Then each
+// lane pulls its new entry: the candidate's key, or the list entry shifted
+// up by the candidates before it.
 __device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint32_t k, int lane) {
-    unsigned long long cm = __ballot(cand && key < ws.kth);
-    while (cm) {
-        const int src = __ffsll((long long)cm) - 1;
-        cm &= cm - 1;
-        const uint64_t kk = shfl64(key, src);
-        if (kk >= ws.kth) continue;
-        const uint32_t p = (uint32_t)__popcll(__ballot(ws.wl < kk));
-        const uint64_t sh = shfl64_up1(ws.wl);
-        if ((uint32_t)lane > p) ws.wl = sh;
-        else if ((uint32_t)lane == p) ws.wl = kk;
-        if ((uint32_t)lane >= k) ws.wl = ~0ull;
-        ws.kth = shfl64(ws.wl, (int)k - 1);
+    const bool in = cand && key < ws.kth;
+    const unsigned long long cm = __ballot(in);
+    if (!cm) return;
+    uint32_t before = 0;  // candidates placed before this position
+    int from = -1;        // the candidate lane placed at this position
+    for (unsigned long long m = cm; m; m &= m - 1) {
+        const int src = __ffsll((long long)m) - 1;
+        const uint64_t kk = bcast64(key, src);
+        const uint32_t pos = (uint32_t)__popcll(__ballot(ws.wl < kk)) +
+                             (uint32_t)__popcll(__ballot(in && key < kk));
+        before += (pos < (uint32_t)lane) ? 1u : 0u;
+        if (pos == (uint32_t)lane) from = src;
     }
+    const int li = lane - (int)before;  // the list entry that moves here otherwise
+    const uint32_t clo = (uint32_t)__shfl((int)(uint32_t)key, from < 0 ? 0 : from, 64);
+    const uint32_t chi = (uint32_t)__shfl((int)(uint32_t)(key >> 32), from < 0 ? 0 : from, 64);
+    const uint32_t llo = (uint32_t)__shfl((int)(uint32_t)ws.wl, li, 64);
+    const uint32_t lhi = (uint32_t)__shfl((int)(uint32_t)(ws.wl >> 32), li, 64);
+    const uint64_t v = (from >= 0) ? (((uint64_t)chi << 32) | clo) : (((uint64_t)lhi << 32) | llo);
+    ws.wl = ((uint32_t)lane < k) ? v : ~0ull;
+    ws.kth = bcast64(ws.wl, (int)k - 1);
 }
 
 // Load the group rows of 4 consecutive member slots (4*RP uint16, 16-byte

@@ -163,7 +163,7 @@ __device__ inline uint64_t bcast64(uint64_t v, int src) {
 }
 
 // Insert the keys flagged in `cand` into the wavefront's sorted top-k list,
-// all at once.  Each candidate below the k-th key is broadcast in turn
+// all at once (called with every lane of the wavefront active).  Each candidate below the k-th key is broadcast in turn
 // (readlane) and its place in the merged order found by ballot (its rank
 // among the list plus its rank among the candidates); every output position
 // notes which candidate lands on it and how many land before it.  Then each
@@ -173,6 +173,25 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint3
     const bool in = cand && key < ws.kth;
     const unsigned long long cm = __ballot(in);
     if (!cm) return;
+    if (bcast64(ws.wl, 0) == ~0ull) {
+        // empty list: rank the candidates among themselves (keys are
+        // distinct; equal ones would be ordered by lane), give the other
+        // lanes the places after them, and permute every key to its rank
+        uint32_t rank = 0;
+        for (unsigned long long m = cm; m; m &= m - 1) {
+            const int src = __ffsll((long long)m) - 1;
+            const uint64_t kk = bcast64(key, src);
+            rank += (kk < key || (kk == key && src < lane)) ? 1u : 0u;
+        }
+        const uint32_t c = (uint32_t)__popcll(cm);
+        const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+        const uint32_t dest = in ? rank : c + (uint32_t)__popcll(~cm & below);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)key);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)(key >> 32));
+        ws.wl = ((uint32_t)lane < (c < k ? c : k)) ? (((uint64_t)hi << 32) | lo) : ~0ull;
+        ws.kth = bcast64(ws.wl, (int)k - 1);
+        return;
+    }
     uint32_t before = 0;  // candidates placed before this position
     int from = -1;        // the candidate lane placed at this position
     for (unsigned long long m = cm; m; m &= m - 1) {

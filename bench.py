@@ -436,6 +436,8 @@ def main():
                    "persistent": bool(args.persistent),
                    "K_L": "tuned (fastest reaching R1@10 >= 0.9)" if w.tuned else "as configured"},
         "build_s": round(w.build_s, 3),
+        "srp_rechecked_fraction": (round(w.index.info.srp_rechecked / (w.cfg["N"] * w.K * w.L), 6)
+                                   if w.dense else None),
         "stages_ms": {"hash": round(hash_ms, 4), "count_decode": round(decode_ms, 4)},
         "roofline": roof,
     }

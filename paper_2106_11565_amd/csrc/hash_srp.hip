@@ -241,6 +241,159 @@ __global__ __launch_bounds__(64 * WM * WN) void srp_mfma_kernel(
     if ((lane % 16) == 0 && flagged) atomicAdd(nflag, flagged);
 }
 
+// The same products for one bf16 operand plane with both operands staged in
+// LDS: a 256-thread workgroup computes a 128 x 128 tile (four wavefronts of
+// 64 x 64); each 32-wide k slice of the 128 rows and the 128 hyperplanes is
+// loaded once per workgroup (two 16-byte loads per thread and operand),
+// prefetched into registers while the previous slice is multiplied, and
+// double-buffered in LDS with rows padded against bank conflicts.
+// Accumulation is chunked: every LCH consecutive slices accumulate into a
+// fresh partial (MFMA accumulate), and the partials are added in fp32 by the
+// wavefront.  A product then passes through at most LCH*32 roundings inside
+// its chunk (whatever order an instruction sums its 32 products and its
+// accumulator in) plus one per chunk, so |v32 - v| <= gamma_m * sum|x_i w_i|
+// with m = min(LCH*32, d) + ceil(d / (LCH*32)) (srp_lds_terms), far below
+// the gamma_d of one long accumulation chain.
+constexpr int LT = 128;          // tile rows and hyperplanes
+constexpr int LK = 32;           // k slice
+constexpr int LROW = LK + 8;     // bf16 per LDS row (16 bytes of padding)
+constexpr int LCH = 4;           // slices per accumulation chunk
+
+// Roundings a product passes through in srp_mfma_lds_kernel (see above).
+inline uint32_t srp_lds_terms(uint32_t dpad) {
+    const uint32_t chunk = LCH * LK;
+    return (dpad < chunk ? dpad : chunk) + (dpad + chunk - 1) / chunk;
+}
+
+__global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
+    const uint16_t *__restrict__ planes, uint32_t ld, const uint16_t *__restrict__ w,
+    uint32_t dpad, const float *__restrict__ nx, const float *__restrict__ nw, uint64_t n,
+    uint32_t H, uint32_t Hw, float gamma, float tau_abs, uint16_t *__restrict__ bits16,
+    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag) {
+    __shared__ __align__(16) uint16_t sa[2][LT * LROW];
+    __shared__ __align__(16) uint16_t sb[2][LT * LROW];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm = wave / 2, wn = wave % 2;
+    const uint64_t tr0 = (uint64_t)blockIdx.y * LT;
+    const uint32_t tc0 = blockIdx.x * LT;
+
+    // this thread's two 16-byte pieces of each operand slice: piece u covers
+    // tile row u / 4, k offset 8 * (u % 4), for u = tid and tid + 256 (named
+    // registers and no branches, so the prefetch stays in registers)
+    const int u0 = tid, u1 = tid + 256;
+    const int rr0 = u0 / 4, rr1 = u1 / 4, kk0 = 8 * (u0 % 4), kk1 = 8 * (u1 % 4);
+    const uint64_t r0 = (tr0 + rr0 < n) ? tr0 + rr0 : n - 1;
+    const uint64_t r1 = (tr0 + rr1 < n) ? tr0 + rr1 : n - 1;
+    const uint32_t c0 = (tc0 + rr0 < H) ? tc0 + rr0 : H - 1;
+    const uint32_t c1 = (tc0 + rr1 < H) ? tc0 + rr1 : H - 1;
+    const uint16_t *ga0 = planes + r0 * ld + kk0;
+    const uint16_t *ga1 = planes + r1 * ld + kk1;
+    const uint16_t *gb0 = w + (uint64_t)c0 * dpad + kk0;
+    const uint16_t *gb1 = w + (uint64_t)c1 * dpad + kk1;
+    const int so0 = rr0 * LROW + kk0, so1 = rr1 * LROW + kk1;
+
+    uint4 ra0 = *reinterpret_cast<const uint4 *>(ga0);
+    uint4 ra1 = *reinterpret_cast<const uint4 *>(ga1);
+    uint4 rb0 = *reinterpret_cast<const uint4 *>(gb0);
+    uint4 rb1 = *reinterpret_cast<const uint4 *>(gb1);
+    *reinterpret_cast<uint4 *>(&sa[0][so0]) = ra0;
+    *reinterpret_cast<uint4 *>(&sa[0][so1]) = ra1;
+    *reinterpret_cast<uint4 *>(&sb[0][so0]) = rb0;
+    *reinterpret_cast<uint4 *>(&sb[0][so1]) = rb1;
+    __syncthreads();
+
+    f32x4 acc[4][4], part[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            part[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    const int lr = lane % 16, lk = (lane / 16) * 8;
+
+    for (uint32_t k0 = 0; k0 < dpad; k0 += LK) {
+        const uint32_t step = k0 / LK;
+        const int cur = step & 1;
+        // next slice (the last iteration reloads its own slice into the
+        // buffer nobody reads any more)
+        const uint32_t kn = (k0 + LK < dpad) ? k0 + LK : k0;
+        ra0 = *reinterpret_cast<const uint4 *>(ga0 + kn);
+        ra1 = *reinterpret_cast<const uint4 *>(ga1 + kn);
+        rb0 = *reinterpret_cast<const uint4 *>(gb0 + kn);
+        rb1 = *reinterpret_cast<const uint4 *>(gb1 + kn);
+        const uint16_t *ca = sa[cur];
+        const uint16_t *cb = sb[cur];
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            fa[a] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&ca[(wm * 64 + 16 * a + lr) * LROW + lk]));
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            fb[b] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&cb[(wn * 64 + 16 * b + lr) * LROW + lk]));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                part[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], part[a][b], 0, 0, 0);
+        if ((step + 1) % LCH == 0 || k0 + LK >= dpad) {
+            // close the chunk: one fp32 addition per output
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[a][b][i] += part[a][b][i];
+                    part[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        uint16_t *na = sa[cur ^ 1];
+        uint16_t *nb = sb[cur ^ 1];
+        *reinterpret_cast<uint4 *>(&na[so0]) = ra0;
+        *reinterpret_cast<uint4 *>(&na[so1]) = ra1;
+        *reinterpret_cast<uint4 *>(&nb[so0]) = rb0;
+        *reinterpret_cast<uint4 *>(&nb[so1]) = rb1;
+        __syncthreads();
+    }
+
+    // Epilogue: trusted sign bits and flags, 16 columns per ballot group.
+    const uint64_t row0 = tr0 + (uint64_t)wm * 64;
+    const uint32_t col0 = tc0 + wn * 64;
+    unsigned long long flagged = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t cbase = col0 + 16 * b;
+        if (cbase >= H) continue;
+        const uint32_t col = cbase + lr;
+        const float wn_ = (col < H) ? nw[col] : 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
+                const float xn = (row < n) ? nx[row] : 0.f;
+                const float v = acc[a][b][i];
+                const float tau = gamma * xn * wn_ + tau_abs;
+                const bool ok = (col < H) && (fabsf(v) > tau);
+                const bool bit = ok && (v > 0.f);
+                const bool flg = (col < H) && !ok;
+                const unsigned long long mb = __ballot(bit);
+                const unsigned long long mf = __ballot(flg);
+                if ((lane % 16) == 0 && row < n) {
+                    const int g = lane / 16;
+                    const uint64_t o = row * (2 * (uint64_t)Hw) + cbase / 16;
+                    bits16[o] = (uint16_t)(mb >> (16 * g));
+                    flags16[o] = (uint16_t)(mf >> (16 * g));
+                    flagged += __popcll((mf >> (16 * g)) & 0xFFFFull);
+                }
+            }
+        }
+    }
+    if ((lane % 16) == 0 && flagged) atomicAdd(nflag, flagged);
+}
+
 // ---------------------------------------------------------------------------
 // Exact sign of sum_i x_i * w_i when FP64 cannot certify it.  Every product
 // is an exact double m * 2^e with |m| < 2^31 and e >= -151 (x: fp32/bf16,
@@ -524,11 +677,13 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     const uint32_t ld = inplace ? d : dpad;
     const uint64_t pstride = (uint64_t)n * dpad;
 
-    const double nterms = (double)nsplit * dpad;
+    // roundings a product can pass through: one long chain of nsplit * dpad
+    // terms for the direct kernel; chunked for the LDS kernel (bf16)
+    const double nterms = nsplit == 1 ? (double)srp_lds_terms(dpad) : (double)nsplit * dpad;
     const double u = 0x1p-23;
     const double gam = nterms * u / (1.0 - nterms * u) * (1.0 + 0x1p-6);
     const float gamma = (float)gam;
-    const float tau_abs = (float)(nterms * 0x1p-100);
+    const float tau_abs = (float)((double)nsplit * dpad * 0x1p-100);
 
     constexpr int MR = 4, NR = 4, WM = 2, WN = 2;
     dim3 grid((H + 16 * NR * WN - 1) / (16 * NR * WN),
@@ -540,8 +695,9 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
                            reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
                            nflag);
     else
-        hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 1>), grid, dim3(64 * WM * WN), 0, s,
-                           pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
+        hipLaunchKernelGGL(srp_mfma_lds_kernel,
+                           dim3((H + LT - 1) / LT, (unsigned)((n + LT - 1) / LT)), dim3(256), 0, s,
+                           pl, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
                            reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
                            nflag);
     FL_CHECK_LAUNCH();

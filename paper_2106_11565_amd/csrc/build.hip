@@ -38,7 +38,9 @@ struct GroupKeys {
     uint64_t k[16][4];
 };
 
-// grp[x*Rp + r] = P_r(x) mod B (padding repetitions R..Rp-1 hold 0).
+// grp[x*Rp + r] = P_r(x) mod B; the padding repetitions R..Rp-1 repeat
+// repetition R-1's group, so a reader may take the minimum over all Rp
+// entries (a repeated cell changes neither the minimum nor its cell).
 __global__ void groups_kernel(uint64_t N, uint32_t R, uint32_t Rp, uint32_t B, uint32_t half,
                               GroupKeys gk, uint16_t *__restrict__ grp) {
     const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,7 +50,7 @@ __global__ void groups_kernel(uint64_t N, uint32_t R, uint32_t Rp, uint32_t B, u
         while (y >= N) y = feistel(y, half, gk.k[r]);
         grp[x * Rp + r] = (uint16_t)(y % B);
     }
-    for (uint32_t r = R; r < Rp; ++r) grp[x * Rp + r] = 0;
+    for (uint32_t r = R; r < Rp; ++r) grp[x * Rp + r] = grp[x * Rp + R - 1];
 }
 
 __global__ void member_keys_kernel(const uint16_t *__restrict__ grp, uint64_t N, uint32_t Rp,

@@ -39,7 +39,8 @@ namespace flinng {
 // over.
 constexpr uint32_t HC_MAX = 32;
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
-constexpr uint32_t CL = 1024;      // positive-cell list capacity
+// positive-cell list capacity (at least two rounds of T cells)
+__host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 512u : 1024u; }
 
 struct QArgs {
     const uint32_t *codes;
@@ -53,6 +54,7 @@ struct QArgs {
     uint32_t mstride;      // member slots per cell (multiple of 4)
     uint32_t threads;      // workgroup size the kernel is launched with
     uint32_t hc;           // histogram copies (a power of two)
+    float inv_bp;          // 1 / Bp, for cell id -> repetition
     uint32_t *ids;
     uint32_t *scores;
     uint8_t *counts_out;   // debug: write counters and skip decode
@@ -69,10 +71,11 @@ struct QLayout {
     size_t off_cnt, off_hist, off_pre, off_start, off_end, off_buf, off_lb, off_lp, off_misc, total;
 };
 
+// gk: the general-k decode, which also needs the per-thread prefix slots.
 __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp, uint32_t cap,
-                                            int T, uint32_t hc) {
+                                            int T, uint32_t hc, bool gk) {
     QLayout l;
-    l.cnt_words = (R * Bp) / 4;
+    l.cnt_words = ((R * Bp) / 4 + 3) & ~3u;  // whole 16-byte units
     l.hist_words = hc * R * (L + 1);
     l.cap = cap;
     size_t o = 0;
@@ -81,8 +84,8 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
     l.off_end = o;   o += (size_t)L * 4;
-    l.off_lb = o;    o += CL * 4;
-    l.off_lp = o;    o += (size_t)T * 4;
+    l.off_lb = o;    o += cl_for(T) * 4;
+    l.off_lp = o;    o += gk ? (size_t)T * 4 : 0;
     l.off_misc = o;  o += 64 * 4;
     l.off_hist = o;  o += (size_t)l.hist_words * 4;  // last: only its size varies with hc
     l.total = (o + 15) & ~(size_t)15;
@@ -92,6 +95,15 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 // misc slots
 enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
        M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_SCAN0 };
+
+// c / d for c < 2^24 and d >= 1, from the float quotient (within one of the
+// true quotient: c is exact in float and the two roundings of c * (1/d)
+// perturb it by less than one for d >= 2; d = 1 is exact) and one correction.
+__device__ inline uint32_t div_small(uint32_t c, uint32_t d, float inv) {
+    uint32_t q = (uint32_t)((float)c * inv);
+    const int32_t rr = (int32_t)(c - q * d);
+    return rr < 0 ? q - 1 : (rr >= (int32_t)d ? q + 1 : q);
+}
 
 template <int T>
 __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *scr, uint32_t *total) {
@@ -243,7 +255,9 @@ __device__ inline uint32_t row_group(const uint32_t (&w)[2 * RP], int e, int r) 
 // with m >= level (all keys when `keep`) go into the wavefront's top-k.
 // Work items are (cell, 256-member chunk); each lane takes 4 consecutive
 // members (one 16-byte id load plus RP/2 16-byte row loads) and keeps U items
-// in flight.
+// in flight.  The loads are unconditional (slots past an item's end, or of an
+// item past the last, read the cell's first slots and are marked invalid), so
+// that all U items' loads are issued before any of them is waited on.
 template <int RP, int U, int T>
 __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32_t *__restrict__ memr,
                                   const uint16_t *__restrict__ cmgr, const uint8_t *cnt8, uint32_t R,
@@ -258,49 +272,51 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
         uint32_t nv[U];
 #pragma unroll
         for (int g = 0; g < U; ++g) {
+            // wavefront-uniform item; the last item stands in past the end
             const uint32_t i = i0 + (uint32_t)g * TW;
-            nv[g] = 0;
-            idv[g] = make_uint4(0, 0, 0, 0);
+            const uint32_t ic = i < nitems ? i : nitems - 1;
+            const uint32_t bb = lbs[ic / cpc];
+            const uint32_t j0 = (ic % cpc) * 256;
+            const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
+            const uint32_t j = j0 + 4 * lane;
+            nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
+            if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
+            const uint64_t slot = (uint64_t)bb * mstride + (j < sz ? j : 0u);
+            idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
+            load_rows<RP>(cmgr + slot * RP, rows[g]);
+        }
+        // repetition r's counters start at rb[r]; the padding repetitions
+        // r >= R repeat repetition R-1 (its group is repeated in the rows)
+        uint32_t rb[RP], xr[RP];
 #pragma unroll
-            for (int w = 0; w < 2 * RP; ++w) rows[g][w] = 0;
-            if (i < nitems) {
-                const uint32_t bb = lbs[i / cpc];
-                const uint32_t j = (i % cpc) * 256 + 4 * lane;
-                const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
-                if (j < sz) {
-                    nv[g] = (sz - j < 4) ? sz - j : 4u;
-                    const uint64_t slot = (uint64_t)bb * mstride + j;
-                    idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
-                    load_rows<RP>(cmgr + slot * RP, rows[g]);
-                }
-            }
+        for (int r = 0; r < RP; ++r) {
+            rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
+            xr[r] = 0xFFFFFFu - rb[r];
         }
 #pragma unroll
         for (int g = 0; g < U; ++g) {
-            uint32_t c = nv[g];
-            for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
-            ws.members += c;
             const uint32_t xs[4] = {idv[g].x, idv[g].y, idv[g].z, idv[g].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const bool val = (uint32_t)e < nv[g];
-                uint32_t m = 0xFFFFFFFFu, cs = 0;
+                // t = (m << 24) | (0xFFFFFF - c*): the minimum over the
+                // member's cells of (count, 0xFFFFFF - cell) is the smallest
+                // count and, among equal counts, the largest cell id (cell
+                // ids stay below 2^24: the counters of all cells fit in LDS)
+                uint32_t t = 0xFFFFFFFFu;
 #pragma unroll
                 for (int r = 0; r < RP; ++r) {
-                    if ((uint32_t)r < R) {
-                        const uint32_t cc = r * Bp + row_group<RP>(rows[g], e, r);
-                        const uint32_t v = cnt8[cc];
-                        if (v <= m) {  // later repetitions have larger cell ids
-                            m = v;
-                            cs = cc;
-                        }
-                    }
+                    const uint32_t gr = row_group<RP>(rows[g], e, r);
+                    const uint32_t v = cnt8[rb[r] + gr];
+                    const uint32_t tv = (v << 24) | (xr[r] - gr);
+                    t = tv < t ? tv : t;
                 }
-                const bool ge = val && m >= level;
+                const bool ge = val && t >= (level << 24);
                 const bool take = val && (keep || ge);
                 ws.n_ge += (uint32_t)__popcll(__ballot(ge));
                 ws.n_all += (uint32_t)__popcll(__ballot(take));
-                const uint64_t key = ((uint64_t)(255u - (m & 255u)) << 56) | ((uint64_t)cs << 32) | xs[e];
+                // high word ~t = ((255 - m) << 24) | c*
+                const uint64_t key = ((uint64_t)(~t) << 32) | xs[e];
                 wave_insert(ws, key, take, k, lane);
             }
         }
@@ -323,14 +339,18 @@ __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t B
 }
 
 // GK: the general-k decode (k > 64) instead of the per-wavefront register
-// top-k; compiled separately so that the common path carries only its own
-// code (and registers).
-template <typename CellT, int RP, int QT, bool GK>
-__global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A) {
+// top-k.  PERS: the persistent grid, whose workgroups pull queries from a
+// device counter; otherwise one workgroup per query.  Each combination is
+// compiled separately so that the common path carries only its own code and
+// registers (the persistent loop keeps more values live).  WAVES: the
+// wavefronts per SIMD the register allocation must allow.
+template <typename CellT, int RP, int QT, bool GK, bool PERS, int WAVES>
+__global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
     constexpr int QW = QT / 64;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t HC = A.hc;
-    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap, QT, HC);
+    const QLayout lay = q_layout(A.L, A.R, A.Bp, A.cap, QT, HC, GK);
+    constexpr uint32_t CL = cl_for(QT);
     uint64_t *buf = reinterpret_cast<uint64_t *>(lds + lay.off_buf);
     uint32_t *cnt32 = reinterpret_cast<uint32_t *>(lds + lay.off_cnt);
     const uint8_t *cnt8 = lds + lay.off_cnt;
@@ -354,7 +374,7 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
 
     uint64_t q = blockIdx.x;
     for (;;) {
-        if (A.work) {
+        if constexpr (PERS) {
             if (tid == 0) misc[M_Q] = atomicAdd(A.work, 1u);
             __syncthreads();
             q = misc[M_Q];
@@ -372,7 +392,10 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
             st = o[0];
             en = o[1];
         }
-        for (uint32_t w = tid; w < lay.cnt_words; w += QT) cnt32[w] = 0u;
+        {
+            uint4 *c16 = reinterpret_cast<uint4 *>(cnt32);
+            for (uint32_t w = tid; w < lay.cnt_words / 4; w += QT) c16[w] = make_uint4(0, 0, 0, 0);
+        }
         for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
         if (en > st) nch = (en + CE - 1) / CE - st / CE;
         uint32_t total;  // chunks over all tables
@@ -390,6 +413,12 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
         // only grow, so after one binary search its table index only moves
         // forward.  Four aligned 16-byte chunks per thread are loaded before
         // their increments; entries outside the table's list are skipped.
+        // With few entries for the number of cells (sparse), each increment
+        // also adds one to the count-at-least histogram of the cell's
+        // repetition at the new count (the old count comes back from the
+        // atomic), which replaces the scan of all counters below.
+        const bool sparse = (uint64_t)total * CE <= lay.cnt_words;
+        uint32_t *hwc = hist + ((uint32_t)tid & (HC - 1)) * R * (L + 1);
         {
             const uint4 *cells16 = static_cast<const uint4 *>(A.cells);
             uint32_t t = 0;
@@ -428,7 +457,16 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
                         const uint32_t j = chunk[u] * CE + e;
                         const uint32_t c = (CE == 8) ? ((w4[e / 2] >> (16 * (e & 1))) & 0xFFFFu)
                                                      : w4[e % 4];
-                        if (j >= lo && j < hi) atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
+                        if (j >= lo && j < hi) {
+                            const uint32_t sh = 8 * (c & 3);
+                            if (sparse) {
+                                const uint32_t old = atomicAdd(&cnt32[c >> 2], 1u << sh);
+                                const uint32_t r = div_small(c, Bp, A.inv_bp);
+                                atomicAdd(&hwc[r * (L + 1) + ((old >> sh) & 255u) + 1], 1u);
+                            } else {
+                                atomicAdd(&cnt32[c >> 2], 1u << sh);
+                            }
+                        }
                     }
                 }
             }
@@ -440,17 +478,18 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
             uint8_t *out = A.counts_out + q * (uint64_t)R * B;
             for (uint32_t c = tid; c < R * B; c += QT) out[c] = cnt8[(c / B) * Bp + c % B];
             __syncthreads();
-            if (!A.work) break;
+            if constexpr (!PERS) break;
             continue;
         }
 
-        // ---- 3. per-repetition histograms of nonzero counts
-        {
-            uint32_t *hw = hist + ((uint32_t)tid & (HC - 1)) * R * (L + 1);
+        // ---- 3. per-repetition histograms of nonzero counts (dense: a scan
+        // of the counters; sparse: already built, as counts-at-least)
+        if (!sparse) {
+            uint32_t *hw = hwc;
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
                 const uint32_t v = cnt32[w];
                 if (!v) continue;
-                const uint32_t r = (4 * w) / Bp;
+                const uint32_t r = div_small(4 * w, Bp, A.inv_bp);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t cv = (v >> (8 * j)) & 255u;
@@ -475,6 +514,9 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
         __syncthreads();
         // suffix sums per repetition (one wavefront per repetition, 4 levels
         // per lane): hist[r][v] = cells of repetition r with count >= v
+        if (sparse) {
+            for (uint32_t r = tid; r < R; r += QT) hist[r * (L + 1)] = B;
+        } else
         for (uint32_t r = wave; r < R; r += QW) {
             uint32_t *h = hist + r * (L + 1);
             uint32_t v[4], loc = 0;
@@ -601,6 +643,9 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
             // items with several in flight per lane and keeps its own top-k
             // in registers; the lists are merged by rank at the end.
             WaveState ws{~0ull, ~0ull, 0u, 0u, 0u};
+            // walk items in flight per lane: one where the rows are wide or
+            // many wavefronts share a SIMD
+            constexpr int WU = (RP >= 4 || (QT == 256 && !PERS)) ? 1 : 2;
             const uint32_t nrep = hist[rep * (L + 1) + level];
             if (nrep <= CL) {
                 for (uint32_t w = tid; w < Bp / 4; w += QT) {
@@ -614,8 +659,8 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
                     }
                 }
                 __syncthreads();
-                walk_cells<RP, (RP >= 8 ? 1 : 2), QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride,
-                                                  level, keep, q0, rem, cpc, k, lane, wave, ws);
+                walk_cells<RP, WU, QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep, q0,
+                                       rem, cpc, k, lane, wave, ws);
             } else {
                 const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
                 for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
@@ -629,8 +674,8 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
                     __syncthreads();
                     const uint32_t nl = misc[M_LCNT];
                     if (nl > CL - QT || cb0 + QT >= B) {
-                        walk_cells<RP, (RP >= 8 ? 1 : 2), QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride,
-                                                          level, keep, q0, rem, cpc, k, lane, wave, ws);
+                        walk_cells<RP, WU, QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
+                                               q0, rem, cpc, k, lane, wave, ws);
                         __syncthreads();
                         if (tid == 0) misc[M_LCNT] = 0;
                         __syncthreads();
@@ -826,17 +871,19 @@ __global__ __launch_bounds__(QT, (QT == 256 ? 4 : 1)) void query_kernel(QArgs A)
             atomicAdd(&A.stats[4], (unsigned long long)misc[M_ST_FINAL]);
         }
         __syncthreads();
-        if (!A.work) break;
+        if constexpr (!PERS) break;
     }
 }
 
 // ---------------------------------------------------------------------------
 uint32_t query_max_k() { return 4096; }
 
-// Top-k buffer capacity: room for k kept keys plus one round of T appends
-// (general path), and for the fast path's per-wave lists at buf[64..).
+// Top-k buffer capacity.  Fast path: the k <= 64 results at buf[0, 64) and
+// one 64-key list per wavefront after them.  General path: room for k kept
+// keys plus one round of T appends, a power of two for the bitonic sort.
 static uint32_t cap_for(uint32_t k, int T) {
-    uint32_t need = std::max<uint32_t>(std::max<uint32_t>(512u, k + (uint32_t)T), 64u + (uint32_t)T);
+    if (k <= 64) return 64u + (uint32_t)T;
+    uint32_t need = std::max<uint32_t>(512u, k + (uint32_t)T);
     uint32_t c = 1;
     while (c < need) c <<= 1;
     return c;
@@ -859,20 +906,21 @@ static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
     const size_t lim = (size_t)max_lds();
     const size_t bins = (size_t)R * (L + 1) * 4;
     QShape sh;
-    const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256, 1).total;
+    const bool gk = k > 64;
+    const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256, 1, gk).total;
     if (small * 4 <= lim) {
         // a state this small holds few cells, so few counts collide: four
         // copies (more only add clearing and merging)
         sh.T = 256;
         sh.hc = (uint32_t)std::min<size_t>(4, 1 + (lim / 4 - small) / bins);
     } else {
-        const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024, 1).total;
+        const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024, 1, gk).total;
         sh.T = big <= lim ? 1024 : 256;
         sh.hc = big <= lim ? (uint32_t)std::min<size_t>(HC_MAX, 1 + (lim - big) / bins) : 1u;
     }
     while (sh.hc & (sh.hc - 1)) sh.hc &= sh.hc - 1;  // round down to a power of two
     sh.cap = cap_for(k, sh.T);
-    sh.lds = q_layout(L, R, Bp, sh.cap, sh.T, sh.hc).total;
+    sh.lds = q_layout(L, R, Bp, sh.cap, sh.T, sh.hc, gk).total;
     return sh;
 }
 
@@ -907,14 +955,20 @@ static int num_cus() {
     return v;
 }
 
-template <typename CellT, int RP, int QT, bool GK>
-static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
+template <typename CellT, int RP, int QT, bool GK, bool PERS, int WAVES>
+static void launch_kernel(const QArgs &a, size_t lds, unsigned grid, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
+        (void)hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK, PERS, WAVES>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
         attr_set = true;
     }
+    hipLaunchKernelGGL((query_kernel<CellT, RP, QT, GK, PERS, WAVES>), dim3(grid), dim3(QT), lds, s, a);
+}
+
+template <typename CellT, int RP, int QT, bool GK>
+static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s) {
     uint64_t grid = a.nq;
     if (persistent) {
         const uint64_t per_cu = std::max<uint64_t>(
@@ -923,7 +977,23 @@ static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s
     }
     if (grid == 0) return;
     if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
-    hipLaunchKernelGGL((query_kernel<CellT, RP, QT, GK>), dim3((unsigned)grid), dim3(QT), lds, s, a);
+    // Register budgets: the one-query fast kernel at 256 threads asks for as
+    // many wavefronts per SIMD as the LDS lets share a CU (six or seven
+    // four-wavefront workgroups); the others take what they need.
+    if constexpr (QT == 256 && !GK) {
+        if (persistent)
+            launch_kernel<CellT, RP, QT, GK, true, 4>(a, lds, (unsigned)grid, s);
+        else if (lds * 7 <= (size_t)max_lds())
+            launch_kernel<CellT, RP, QT, GK, false, 7>(a, lds, (unsigned)grid, s);
+        else
+            launch_kernel<CellT, RP, QT, GK, false, 6>(a, lds, (unsigned)grid, s);
+    } else {
+        constexpr int W = QT == 256 ? 4 : 1;
+        if (persistent)
+            launch_kernel<CellT, RP, QT, GK, true, W>(a, lds, (unsigned)grid, s);
+        else
+            launch_kernel<CellT, RP, QT, GK, false, W>(a, lds, (unsigned)grid, s);
+    }
     FL_CHECK_LAUNCH();
 }
 
@@ -971,6 +1041,7 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.cap = sh.cap;
     a.hc = sh.hc;
     a.mstride = ix.mstride;
+    a.inv_bp = 1.0f / (float)a.Bp;
     a.budget = BUDGET;
     return a;
 }
@@ -984,7 +1055,7 @@ void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint3
     a.scores = scores_dev;
     a.work = persistent ? work_counter : nullptr;
     a.stats = stats;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc, a.k > 64).total;
     if ((int)lds > max_lds())
         fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +
                                 " bytes) exceeds the workgroup LDS limit; reduce B*R or k");
@@ -1000,7 +1071,7 @@ void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint
     if (nq == 0) return;
     QArgs a = make_args(ix, codes_dev, nq, 1);
     a.counts_out = counts_dev;
-    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc).total;
+    const size_t lds = q_layout(a.L, a.R, a.Bp, a.cap, (int)a.threads, a.hc, a.k > 64).total;
     if ((int)lds > max_lds()) fail(FLINNG_EINVAL, "per-query state exceeds the LDS limit");
     if (ix.cell_bytes == 2)
         launch_q<uint16_t>(a, lds, false, s);

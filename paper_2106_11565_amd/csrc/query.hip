@@ -39,8 +39,8 @@ namespace flinng {
 // over.
 constexpr uint32_t HC_MAX = 32;
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
-// positive-cell list capacity (at least two rounds of T cells)
-__host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 512u : 1024u; }
+// positive-cell list capacity (at least one round of T cells)
+__host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 256u : 1024u; }
 
 struct QArgs {
     const uint32_t *codes;
@@ -174,8 +174,67 @@ __device__ inline uint64_t bcast64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The value of lane (lane ^ J) (every lane active): quad permutations and a
+// row rotation by 8 move data within the VALU (DPP); the other distances go
+// through the LDS crossbar (swizzle within 32 lanes, permute across halves).
+template <int J>
+__device__ inline uint32_t lane_xor(uint32_t v, int lane) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row rotate 8
+    } else if constexpr (J < 32) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);  // xor J, 32-lane groups
+    } else {
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ J) << 2, (int)v);
+    }
+}
+
+// One compare-exchange step of a bitonic sort across the wavefront: lanes
+// l and l ^ J exchange so that the lower lane keeps the smaller key in
+// ascending blocks (bit S of l clear) and the larger one in descending
+// blocks.
+template <int S, int J>
+__device__ inline uint64_t bitonic_step(uint64_t v, int lane) {
+    const uint32_t plo = lane_xor<J>((uint32_t)v, lane);
+    const uint32_t phi = lane_xor<J>((uint32_t)(v >> 32), lane);
+    const uint64_t p = ((uint64_t)phi << 32) | plo;
+    const bool keep_min = (((uint32_t)lane & S) == 0) == (((uint32_t)lane & J) == 0);
+    return (keep_min == (p < v)) ? p : v;
+}
+
+// Sort one key per lane ascending across the 64 lanes (every lane active).
+__device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
+    v = bitonic_step<2, 1>(v, lane);
+    v = bitonic_step<4, 2>(v, lane);
+    v = bitonic_step<4, 1>(v, lane);
+    v = bitonic_step<8, 4>(v, lane);
+    v = bitonic_step<8, 2>(v, lane);
+    v = bitonic_step<8, 1>(v, lane);
+    v = bitonic_step<16, 8>(v, lane);
+    v = bitonic_step<16, 4>(v, lane);
+    v = bitonic_step<16, 2>(v, lane);
+    v = bitonic_step<16, 1>(v, lane);
+    v = bitonic_step<32, 16>(v, lane);
+    v = bitonic_step<32, 8>(v, lane);
+    v = bitonic_step<32, 4>(v, lane);
+    v = bitonic_step<32, 2>(v, lane);
+    v = bitonic_step<32, 1>(v, lane);
+    v = bitonic_step<64, 32>(v, lane);
+    v = bitonic_step<64, 16>(v, lane);
+    v = bitonic_step<64, 8>(v, lane);
+    v = bitonic_step<64, 4>(v, lane);
+    v = bitonic_step<64, 2>(v, lane);
+    v = bitonic_step<64, 1>(v, lane);
+    return v;
+}
+
 // Insert the keys flagged in `cand` into the wavefront's sorted top-k list,
-// all at once (called with every lane of the wavefront active).  Each candidate below the k-th key is broadcast in turn
+// all at once (called with every lane of the wavefront active).  Into an
+// empty list the candidates are sorted across the wavefront and the first k
+// kept.  Otherwise each candidate below the k-th key is broadcast in turn
 // (readlane) and its place in the merged order found by ballot (its rank
 // among the list plus its rank among the candidates); every output position
 // notes which candidate lands on it and how many land before it.  Then each
@@ -186,21 +245,27 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint3
     const unsigned long long cm = __ballot(in);
     if (!cm) return;
     if (bcast64(ws.wl, 0) == ~0ull) {
-        // empty list: rank the candidates among themselves (keys are
-        // distinct; equal ones would be ordered by lane), give the other
-        // lanes the places after them, and permute every key to its rank
-        uint32_t rank = 0;
-        for (unsigned long long m = cm; m; m &= m - 1) {
-            const int src = __ffsll((long long)m) - 1;
-            const uint64_t kk = bcast64(key, src);
-            rank += (kk < key || (kk == key && src < lane)) ? 1u : 0u;
-        }
+        // empty list: many candidates are sorted across the wavefront (keys
+        // never equal ~0: their cell field is below 2^24 - 1); a few are
+        // ranked among themselves and permuted to their ranks
         const uint32_t c = (uint32_t)__popcll(cm);
-        const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-        const uint32_t dest = in ? rank : c + (uint32_t)__popcll(~cm & below);
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)key);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)(key >> 32));
-        ws.wl = ((uint32_t)lane < (c < k ? c : k)) ? (((uint64_t)hi << 32) | lo) : ~0ull;
+        if (c > 16) {
+            const uint64_t v = wave_sort64(in ? key : ~0ull, lane);
+            ws.wl = ((uint32_t)lane < k) ? v : ~0ull;
+        } else {
+            uint32_t rank = 0;
+            for (unsigned long long m = cm; m; m &= m - 1) {
+                const int src = __ffsll((long long)m) - 1;
+                const uint64_t kk = bcast64(key, src);
+                rank += (kk < key || (kk == key && src < lane)) ? 1u : 0u;
+            }
+            const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+            const uint32_t dest = in ? rank : c + (uint32_t)__popcll(~cm & below);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)key);
+            const uint32_t hi =
+                (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)(key >> 32));
+            ws.wl = ((uint32_t)lane < (c < k ? c : k)) ? (((uint64_t)hi << 32) | lo) : ~0ull;
+        }
         ws.kth = bcast64(ws.wl, (int)k - 1);
         return;
     }
@@ -418,7 +483,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         // repetition at the new count (the old count comes back from the
         // atomic), which replaces the scan of all counters below.
         const bool sparse = (uint64_t)total * CE <= lay.cnt_words;
-        uint32_t *hwc = hist + ((uint32_t)tid & (HC - 1)) * R * (L + 1);
+        // (the sparse increments are few: one copy takes them all)
+        uint32_t *hwc = hist + (sparse ? 0u : ((uint32_t)tid & (HC - 1)) * R * (L + 1));
         {
             const uint4 *cells16 = static_cast<const uint4 *>(A.cells);
             uint32_t t = 0;
@@ -498,6 +564,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             }
         }
         __syncthreads();
+        // merge the copies into copy 0 (sparse: copy 0 holds everything)
+        if (!sparse)
         for (uint32_t i = tid; i < R * (L + 1); i += QT) {
             uint32_t sacc = 0;
             // constant trip counts: a loop bounded by HC alone costs registers
@@ -683,8 +751,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
             }
             // merge the per-wave lists: rank of each key among all lists
-            uint64_t *wlist = buf + 64;
-            wlist[wave * 64 + lane] = ws.wl;
+            uint64_t *wlist = buf + k;  // one k-key list per wavefront
+            if ((uint32_t)lane < k) wlist[wave * k + lane] = ws.wl;
             if (lane == 0) {
                 atomicAdd(&misc[M_NGE], ws.n_ge);
                 atomicAdd(&misc[M_NALL], ws.n_all);
@@ -693,7 +761,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             __syncthreads();
             if ((uint32_t)tid < QW * k) {
                 const uint32_t w = tid / k, i = tid % k;
-                const uint64_t key = wlist[w * 64 + i];
+                const uint64_t key = wlist[w * k + i];
                 if (key != ~0ull) {
                     uint32_t rank = i;
                     for (uint32_t w2 = 0; w2 < (uint32_t)QW; ++w2) {
@@ -701,7 +769,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                         uint32_t lo = 0, hi = k;  // keys of list w2 below `key`
                         while (lo < hi) {
                             const uint32_t mid = (lo + hi) >> 1;
-                            if (wlist[w2 * 64 + mid] < key) lo = mid + 1; else hi = mid;
+                            if (wlist[w2 * k + mid] < key) lo = mid + 1; else hi = mid;
                         }
                         rank += lo;
                     }
@@ -878,11 +946,12 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
 // ---------------------------------------------------------------------------
 uint32_t query_max_k() { return 4096; }
 
-// Top-k buffer capacity.  Fast path: the k <= 64 results at buf[0, 64) and
-// one 64-key list per wavefront after them.  General path: room for k kept
-// keys plus one round of T appends, a power of two for the bitonic sort.
+// Top-k buffer capacity.  Fast path (k <= 64): the k results, then one
+// k-key list per wavefront (an even count, so that the counters after it
+// stay 16-byte aligned).  General path: room for k kept keys plus one round
+// of T appends, a power of two for the bitonic sort.
 static uint32_t cap_for(uint32_t k, int T) {
-    if (k <= 64) return 64u + (uint32_t)T;
+    if (k <= 64) return (k * (1u + (uint32_t)T / 64) + 1) & ~1u;
     uint32_t need = std::max<uint32_t>(512u, k + (uint32_t)T);
     uint32_t c = 1;
     while (c < need) c <<= 1;
@@ -978,11 +1047,13 @@ static void launch_rp(const QArgs &a, size_t lds, bool persistent, hipStream_t s
     if (grid == 0) return;
     if (grid > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "query batch too large for one launch");
     // Register budgets: the one-query fast kernel at 256 threads asks for as
-    // many wavefronts per SIMD as the LDS lets share a CU (six or seven
+    // many wavefronts per SIMD as the LDS lets share a CU (six to eight
     // four-wavefront workgroups); the others take what they need.
     if constexpr (QT == 256 && !GK) {
         if (persistent)
             launch_kernel<CellT, RP, QT, GK, true, 4>(a, lds, (unsigned)grid, s);
+        else if (lds * 8 <= (size_t)max_lds())
+            launch_kernel<CellT, RP, QT, GK, false, 8>(a, lds, (unsigned)grid, s);
         else if (lds * 7 <= (size_t)max_lds())
             launch_kernel<CellT, RP, QT, GK, false, 7>(a, lds, (unsigned)grid, s);
         else

@@ -196,13 +196,25 @@ __device__ inline uint32_t lane_xor(uint32_t v, int lane) {
 // l and l ^ J exchange so that the lower lane keeps the smaller key in
 // ascending blocks (bit S of l clear) and the larger one in descending
 // blocks.
+// Lanes l of a wavefront with bit S of l equal to bit J of l, as a mask
+// (a compile-time constant, rematerialised where it is used).
+constexpr unsigned long long keep_min_mask(int S, int J) {
+    unsigned long long m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (((l & S) == 0) == ((l & J) == 0)) m |= 1ull << l;
+    return m;
+}
+
 template <int S, int J>
 __device__ inline uint64_t bitonic_step(uint64_t v, int lane) {
     const uint32_t plo = lane_xor<J>((uint32_t)v, lane);
     const uint32_t phi = lane_xor<J>((uint32_t)(v >> 32), lane);
     const uint64_t p = ((uint64_t)phi << 32) | plo;
-    const bool keep_min = (((uint32_t)lane & S) == 0) == (((uint32_t)lane & J) == 0);
-    return (keep_min == (p < v)) ? p : v;
+    // take the partner's key where it is smaller in a keep-min lane, or
+    // larger in a keep-max lane
+    constexpr unsigned long long km = keep_min_mask(S, J);
+    const unsigned long long take = ~(__ballot(p < v) ^ km);
+    return __builtin_amdgcn_inverse_ballot_w64(take) ? p : v;
 }
 
 // Sort one key per lane ascending across the 64 lanes (every lane active).
@@ -231,23 +243,23 @@ __device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
     return v;
 }
 
-// Insert the keys flagged in `cand` into the wavefront's sorted top-k list,
-// all at once (called with every lane of the wavefront active).  Into an
-// empty list the candidates are sorted across the wavefront and the first k
-// kept.  Otherwise each candidate below the k-th key is broadcast in turn
-// (readlane) and its place in the merged order found by ballot (its rank
-// among the list plus its rank among the candidates); every output position
-// notes which candidate lands on it and how many land before it.  Then each
-// lane pulls its new entry: the candidate's key, or the list entry shifted
-// up by the candidates before it.
-__device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint32_t k, int lane) {
-    const bool in = cand && key < ws.kth;
-    const unsigned long long cm = __ballot(in);
+// Insert the keys of the lanes in `tk` into the wavefront's sorted top-k
+// list, all at once (called with every lane of the wavefront active; keys
+// are distinct).  Into an empty list many candidates are sorted across the
+// wavefront and the first k kept, a few are ranked among themselves and
+// permuted to their ranks.  Otherwise each candidate below the k-th key is
+// broadcast in turn (readlane) and its place in the merged order found by
+// ballot (its rank among the list plus its rank among the candidates); the
+// places taken form a lane mask and each place notes its candidate.  Then
+// each lane pulls its new entry: the candidate's key, or the list entry
+// shifted up by the candidates placed before it.
+__device__ inline void wave_insert(WaveState &ws, uint64_t key, unsigned long long tk, uint32_t k,
+                                   int lane) {
+    const unsigned long long cm = __ballot(key < ws.kth) & tk;
     if (!cm) return;
+    const bool in = __builtin_amdgcn_inverse_ballot_w64(cm);
     if (bcast64(ws.wl, 0) == ~0ull) {
-        // empty list: many candidates are sorted across the wavefront (keys
-        // never equal ~0: their cell field is below 2^24 - 1); a few are
-        // ranked among themselves and permuted to their ranks
+        // empty list (keys never equal ~0: their cell field is below 2^24 - 1)
         const uint32_t c = (uint32_t)__popcll(cm);
         if (c > 16) {
             const uint64_t v = wave_sort64(in ? key : ~0ull, lane);
@@ -255,12 +267,13 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint3
         } else {
             uint32_t rank = 0;
             for (unsigned long long m = cm; m; m &= m - 1) {
-                const int src = __ffsll((long long)m) - 1;
-                const uint64_t kk = bcast64(key, src);
-                rank += (kk < key || (kk == key && src < lane)) ? 1u : 0u;
+                const uint64_t kk = bcast64(key, __ffsll((long long)m) - 1);
+                rank += (kk < key) ? 1u : 0u;
             }
-            const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-            const uint32_t dest = in ? rank : c + (uint32_t)__popcll(~cm & below);
+            // the other lanes take the places after the candidates, in order
+            const uint32_t dest = in ? rank : c + __builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(~cm >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)~cm, 0u));
             const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)key);
             const uint32_t hi =
                 (uint32_t)__builtin_amdgcn_ds_permute((int)(dest * 4), (int)(uint32_t)(key >> 32));
@@ -269,22 +282,28 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, bool cand, uint3
         ws.kth = bcast64(ws.wl, (int)k - 1);
         return;
     }
-    uint32_t before = 0;  // candidates placed before this position
-    int from = -1;        // the candidate lane placed at this position
+    unsigned long long placed = 0;  // list places taken by candidates
+    int from = 0;                   // the candidate lane placed at this place
     for (unsigned long long m = cm; m; m &= m - 1) {
         const int src = __ffsll((long long)m) - 1;
         const uint64_t kk = bcast64(key, src);
         const uint32_t pos = (uint32_t)__popcll(__ballot(ws.wl < kk)) +
-                             (uint32_t)__popcll(__ballot(in && key < kk));
-        before += (pos < (uint32_t)lane) ? 1u : 0u;
-        if (pos == (uint32_t)lane) from = src;
+                             (uint32_t)__popcll(__ballot(key < kk) & cm);
+        if (pos < k) {
+            placed |= 1ull << pos;
+            from = (lane == (int)pos) ? src : from;
+        }
     }
-    const int li = lane - (int)before;  // the list entry that moves here otherwise
-    const uint32_t clo = (uint32_t)__shfl((int)(uint32_t)key, from < 0 ? 0 : from, 64);
-    const uint32_t chi = (uint32_t)__shfl((int)(uint32_t)(key >> 32), from < 0 ? 0 : from, 64);
+    // candidates placed before this lane; the list entry that moves here
+    const uint32_t before =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(placed >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)placed, 0u));
+    const int li = lane - (int)before;
+    const bool fromc = __builtin_amdgcn_inverse_ballot_w64(placed);
+    const uint32_t clo = (uint32_t)__shfl((int)(uint32_t)key, from, 64);
+    const uint32_t chi = (uint32_t)__shfl((int)(uint32_t)(key >> 32), from, 64);
     const uint32_t llo = (uint32_t)__shfl((int)(uint32_t)ws.wl, li, 64);
     const uint32_t lhi = (uint32_t)__shfl((int)(uint32_t)(ws.wl >> 32), li, 64);
-    const uint64_t v = (from >= 0) ? (((uint64_t)chi << 32) | clo) : (((uint64_t)lhi << 32) | llo);
+    const uint64_t v = fromc ? (((uint64_t)chi << 32) | clo) : (((uint64_t)lhi << 32) | llo);
     ws.wl = ((uint32_t)lane < k) ? v : ~0ull;
     ws.kth = bcast64(ws.wl, (int)k - 1);
 }
@@ -331,7 +350,8 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
                                   int wave, WaveState &ws) {
     constexpr int TW = T / 64;
     const uint32_t nitems = nl * cpc;
-    for (uint32_t i0 = wave; i0 < nitems; i0 += TW * U) {
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    for (uint32_t i0 = wv; i0 < nitems; i0 += TW * U) {
         uint4 idv[U];
         uint32_t rows[U][2 * RP];
         uint32_t nv[U];
@@ -340,8 +360,9 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
             // wavefront-uniform item; the last item stands in past the end
             const uint32_t i = i0 + (uint32_t)g * TW;
             const uint32_t ic = i < nitems ? i : nitems - 1;
-            const uint32_t bb = lbs[ic / cpc];
-            const uint32_t j0 = (ic % cpc) * 256;
+            const uint32_t ci = cpc == 1 ? ic : ic / cpc;
+            const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
+            const uint32_t j0 = (ic - ci * cpc) * 256;
             const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
             const uint32_t j = j0 + 4 * lane;
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
@@ -376,13 +397,16 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
                     const uint32_t tv = (v << 24) | (xr[r] - gr);
                     t = tv < t ? tv : t;
                 }
-                const bool ge = val && t >= (level << 24);
-                const bool take = val && (keep || ge);
-                ws.n_ge += (uint32_t)__popcll(__ballot(ge));
-                ws.n_all += (uint32_t)__popcll(__ballot(take));
+                // lane masks of the valid members, of those with m >= level,
+                // and of those kept
+                const unsigned long long vm = __ballot(val);
+                const unsigned long long gm = __ballot(t >= (level << 24)) & vm;
+                const unsigned long long tm = keep ? vm : gm;
+                ws.n_ge += (uint32_t)__popcll(gm);
+                ws.n_all += (uint32_t)__popcll(tm);
                 // high word ~t = ((255 - m) << 24) | c*
                 const uint64_t key = ((uint64_t)(~t) << 32) | xs[e];
-                wave_insert(ws, key, take, k, lane);
+                wave_insert(ws, key, tm, k, lane);
             }
         }
     }

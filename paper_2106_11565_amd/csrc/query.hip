@@ -774,7 +774,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     }
                 }
             }
-            // merge the per-wave lists: rank of each key among all lists
+            // merge the per-wave lists: when they fit in one wavefront, one
+            // sort across it; else the rank of each key among all lists
             uint64_t *wlist = buf + k;  // one k-key list per wavefront
             if ((uint32_t)lane < k) wlist[wave * k + lane] = ws.wl;
             if (lane == 0) {
@@ -783,7 +784,12 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 atomicAdd(&misc[M_MEMB], ws.members);
             }
             __syncthreads();
-            if ((uint32_t)tid < QW * k) {
+            if (QW * k <= 64) {
+                if (wave == 0) {
+                    const uint64_t v = wave_sort64((uint32_t)lane < QW * k ? wlist[lane] : ~0ull, lane);
+                    if ((uint32_t)lane < k) buf[lane] = v;
+                }
+            } else if ((uint32_t)tid < QW * k) {
                 const uint32_t w = tid / k, i = tid % k;
                 const uint64_t key = wlist[w * k + i];
                 if (key != ~0ull) {

@@ -41,6 +41,8 @@ constexpr uint32_t HC_MAX = 32;
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
 // positive-cell list capacity (at least one round of T cells)
 __host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 256u : 1024u; }
+// capacity of the list of cells a sparse query touched (fast path)
+__host__ __device__ constexpr uint32_t tl_for(int T) { return (uint32_t)T; }
 
 struct QArgs {
     const uint32_t *codes;
@@ -68,7 +70,8 @@ struct QArgs {
 
 struct QLayout {
     uint32_t cnt_words, hist_words, cap;
-    size_t off_cnt, off_hist, off_pre, off_start, off_end, off_buf, off_lb, off_lp, off_misc, total;
+    size_t off_cnt, off_hist, off_pre, off_start, off_end, off_buf, off_lb, off_lp, off_tl, off_misc,
+        total;
 };
 
 // gk: the general-k decode, which also needs the per-thread prefix slots.
@@ -86,6 +89,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_end = o;   o += (size_t)L * 4;
     l.off_lb = o;    o += cl_for(T) * 4;
     l.off_lp = o;    o += gk ? (size_t)T * 4 : 0;
+    l.off_tl = o;    o += gk ? 0 : (size_t)tl_for(T) * 4;
     l.off_misc = o;  o += 64 * 4;
     l.off_hist = o;  o += (size_t)l.hist_words * 4;  // last: only its size varies with hc
     l.total = (o + 15) & ~(size_t)15;
@@ -94,7 +98,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 
 // misc slots
 enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
-       M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_SCAN0 };
+       M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_NT, M_SCAN0 };
 
 // c / d for c < 2^24 and d >= 1, from the float quotient (within one of the
 // true quotient: c is exact in float and the two roundings of c * (1/d)
@@ -449,6 +453,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
     uint32_t *lend = reinterpret_cast<uint32_t *>(lds + lay.off_end);
     uint32_t *lb = reinterpret_cast<uint32_t *>(lds + lay.off_lb);
     uint32_t *lp = reinterpret_cast<uint32_t *>(lds + lay.off_lp);
+    uint32_t *tl = reinterpret_cast<uint32_t *>(lds + lay.off_tl);
+    constexpr uint32_t TLC = tl_for(QT);
     uint32_t *misc = reinterpret_cast<uint32_t *>(lds + lay.off_misc);
     uint32_t *scr = misc + M_SCAN0;
 
@@ -486,6 +492,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             for (uint32_t w = tid; w < lay.cnt_words / 4; w += QT) c16[w] = make_uint4(0, 0, 0, 0);
         }
         for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
+        if (tid == 0) misc[M_NT] = 0;
         if (en > st) nch = (en + CE - 1) / CE - st / CE;
         uint32_t total;  // chunks over all tables
         const uint32_t ex = wg_excl_scan<QT>(nch, scr, &total);
@@ -551,8 +558,16 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                             const uint32_t sh = 8 * (c & 3);
                             if (sparse) {
                                 const uint32_t old = atomicAdd(&cnt32[c >> 2], 1u << sh);
+                                const uint32_t ob = (old >> sh) & 255u;
                                 const uint32_t r = div_small(c, Bp, A.inv_bp);
-                                atomicAdd(&hwc[r * (L + 1) + ((old >> sh) & 255u) + 1], 1u);
+                                atomicAdd(&hwc[r * (L + 1) + ob + 1], 1u);
+                                if constexpr (!GK) {
+                                    // first hit of the cell: note it
+                                    if (ob == 0) {
+                                        const uint32_t slot = atomicAdd(&misc[M_NT], 1u);
+                                        if (slot < TLC) tl[slot] = c;
+                                    }
+                                }
                             } else {
                                 atomicAdd(&cnt32[c >> 2], 1u << sh);
                             }
@@ -740,14 +755,24 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             constexpr int WU = (RP >= 4 || (QT == 256 && !PERS)) ? 1 : 2;
             const uint32_t nrep = hist[rep * (L + 1) + level];
             if (nrep <= CL) {
-                for (uint32_t w = tid; w < Bp / 4; w += QT) {
-                    const uint32_t v = cnt32[rep * (Bp / 4) + w];
-                    if (!v) continue;
+                const uint32_t nt = misc[M_NT];
+                if (sparse && nt <= TLC) {
+                    // from the cells the query touched
+                    const uint32_t c0 = rep * Bp;
+                    for (uint32_t i = tid; i < nt; i += QT) {
+                        const uint32_t c = tl[i];
+                        if (c - c0 < B && cnt8[c] >= level) lb[atomicAdd(&misc[M_LCNT], 1u)] = c - c0;
+                    }
+                } else {
+                    for (uint32_t w = tid; w < Bp / 4; w += QT) {
+                        const uint32_t v = cnt32[rep * (Bp / 4) + w];
+                        if (!v) continue;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t b = 4 * w + j;
-                        if (b < B && ((v >> (8 * j)) & 255u) >= level)
-                            lb[atomicAdd(&misc[M_LCNT], 1u)] = b;
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t b = 4 * w + j;
+                            if (b < B && ((v >> (8 * j)) & 255u) >= level)
+                                lb[atomicAdd(&misc[M_LCNT], 1u)] = b;
+                        }
                     }
                 }
                 __syncthreads();

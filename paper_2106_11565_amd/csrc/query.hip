@@ -52,6 +52,7 @@ struct QArgs {
     const uint32_t *mem;   // [R][B][mstride] member ids
     const uint16_t *cmg;   // [R][B][mstride][Rp] member group rows
     uint64_t N;
+    uint32_t q0, rem;      // group sizes: N / B, and the groups b < N % B hold one more
     uint32_t L, R, Rp, B, Bp, nbits, k, cap;
     uint32_t mstride;      // member slots per cell (multiple of 4)
     uint32_t threads;      // workgroup size the kernel is launched with
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint32_t L = A.L, R = A.R, B = A.B, Bp = A.Bp, k = A.k, cap = A.cap;
     const uint64_t nbk1 = (1ull << A.nbits) + 1;
-    const uint32_t q0 = (uint32_t)(A.N / B), rem = (uint32_t)(A.N % B);
+    const uint32_t q0 = A.q0, rem = A.rem;
     const uint32_t gmax = q0 + (rem ? 1u : 0u);
     const uint32_t cpc = (gmax + 255) / 256;  // 256-member chunks per cell
     const uint64_t rstride = (uint64_t)B * A.mstride;
@@ -495,14 +496,34 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         if (tid == 0) misc[M_NT] = 0;
         if (en > st) nch = (en + CE - 1) / CE - st / CE;
         uint32_t total;  // chunks over all tables
-        const uint32_t ex = wg_excl_scan<QT>(nch, scr, &total);
-        if ((uint32_t)tid < L) {
-            pre[tid] = ex;
-            lstart[tid] = st;
-            lend[tid] = en;
+        if (L <= 64) {
+            // the tables fit in wavefront 0: the scan stays in it
+            if (wave == 0) {
+                uint32_t inc = nch;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
+                    if (lane >= o) inc += y;
+                }
+                if ((uint32_t)lane < L) {
+                    pre[lane] = inc - nch;
+                    lstart[lane] = st;
+                    lend[lane] = en;
+                }
+                if (lane == 63) pre[L] = inc;  // lanes past L add nothing
+            }
+            __syncthreads();
+            total = pre[L];
+        } else {
+            const uint32_t ex = wg_excl_scan<QT>(nch, scr, &total);
+            if ((uint32_t)tid < L) {
+                pre[tid] = ex;
+                lstart[tid] = st;
+                lend[tid] = en;
+            }
+            if (tid == 0) pre[L] = total;
+            __syncthreads();
         }
-        if (tid == 0) pre[L] = total;
-        __syncthreads();
 
         // ---- 2. count: one increment per listed cell per table.  Chunk ci
         // belongs to the last table t with pre[t] <= ci; a thread's chunks
@@ -519,7 +540,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         {
             const uint4 *cells16 = static_cast<const uint4 *>(A.cells);
             uint32_t t = 0;
-            {
+            if ((uint32_t)tid < total) {
                 uint32_t lo = 0, hi = L;
                 const uint32_t idx = tid;
                 while (hi - lo > 1) {
@@ -670,20 +691,15 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         __syncthreads();
         // t_hi = #{t in 1..L : ms[t]*gmax >= k} (a prefix of levels);
         // t_lo = #{t in 1..L : ms[t]*gmax <= budget} (a suffix of levels).
+        // (level t is thread t - 1's: L < QT)
         {
-            uint32_t c_hi = 0, c_lo = 0;
-            for (uint32_t t = 1 + tid; t <= L; t += QT) {
-                const uint64_t sz = (uint64_t)ms[t] * gmax;
-                c_hi += (sz >= k) ? 1u : 0u;
-                c_lo += (sz <= A.budget) ? 1u : 0u;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                c_hi += (uint32_t)__shfl_xor((int)c_hi, o, 64);
-                c_lo += (uint32_t)__shfl_xor((int)c_lo, o, 64);
-            }
-            if (lane == 0) {
-                atomicAdd(&misc[M_THI], c_hi);
-                atomicAdd(&misc[M_NEXT], c_lo);
+            const uint32_t t = 1 + tid;
+            const uint64_t sz = (t <= L) ? (uint64_t)ms[t] * gmax : 0;
+            const unsigned long long mh = __ballot(t <= L && sz >= k);
+            const unsigned long long ml = __ballot(t <= L && sz <= A.budget);
+            if (lane == 0 && (uint32_t)wave * 64 < L) {
+                atomicAdd(&misc[M_THI], (uint32_t)__popcll(mh));
+                atomicAdd(&misc[M_NEXT], (uint32_t)__popcll(ml));
             }
         }
         __syncthreads();
@@ -971,10 +987,11 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 __syncthreads();
                 if (tid == 0) misc[M_NEXT] = 0;
                 __syncthreads();
-                uint32_t c = 0;
-                for (uint32_t t = 1 + tid; t <= L; t += QT) c += ((uint64_t)ms[t] * gmax <= lim) ? 1u : 0u;
-                for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
-                if (lane == 0) atomicAdd(&misc[M_NEXT], c);
+                {
+                    const uint32_t t = 1 + tid;
+                    const unsigned long long ml = __ballot(t <= L && (uint64_t)ms[t] * gmax <= lim);
+                    if (lane == 0 && (uint32_t)wave * 64 < L) atomicAdd(&misc[M_NEXT], (uint32_t)__popcll(ml));
+                }
                 __syncthreads();
                 if (tid == 0) {
                     const uint32_t t1 = L + 1 - misc[M_NEXT];
@@ -1155,6 +1172,8 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.mem = ix.mem;
     a.cmg = ix.cmg;
     a.N = ix.N;
+    a.q0 = (uint32_t)(ix.N / ix.p.B);
+    a.rem = (uint32_t)(ix.N % ix.p.B);
     a.L = ix.p.L;
     a.R = ix.p.R;
     a.Rp = ix.Rp;

@@ -98,7 +98,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 }
 
 // misc slots
-enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_DONE, M_THRLO,
+enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_THRLO,
        M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_NT, M_SCAN0 };
 
 // c / d for c < 2^24 and d >= 1, from the float quotient (within one of the
@@ -608,10 +608,13 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             continue;
         }
 
-        // ---- 3. per-repetition histograms of nonzero counts (dense: a scan
-        // of the counters; sparse: already built, as counts-at-least)
-        if (!sparse) {
-            uint32_t *hw = hwc;
+        // ---- 3. per-repetition histograms, as counts-at-least: hist[r][v] =
+        // cells of repetition r with count >= v (sparse: built while
+        // counting; dense: a scan of the counters into HC copies, the copies
+        // merged, then suffix sums)
+        if (sparse) {
+            for (uint32_t r = tid; r < R; r += QT) hist[r * (L + 1)] = B;
+        } else {
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
                 const uint32_t v = cnt32[w];
                 if (!v) continue;
@@ -619,55 +622,49 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t cv = (v >> (8 * j)) & 255u;
-                    if (cv) atomicAdd(&hw[r * (L + 1) + cv], 1u);
+                    if (cv) atomicAdd(&hwc[r * (L + 1) + cv], 1u);
                 }
             }
-        }
-        __syncthreads();
-        // merge the copies into copy 0 (sparse: copy 0 holds everything)
-        if (!sparse)
-        for (uint32_t i = tid; i < R * (L + 1); i += QT) {
-            uint32_t sacc = 0;
-            // constant trip counts: a loop bounded by HC alone costs registers
-            if (HC <= 4) {
+            __syncthreads();
+            for (uint32_t i = tid; i < R * (L + 1); i += QT) {
+                uint32_t sacc = 0;
+                // constant trip counts: a loop bounded by HC alone costs registers
+                if (HC <= 4) {
 #pragma unroll
-                for (uint32_t w = 0; w < 4; ++w)
-                    if (w < HC) sacc += hist[w * R * (L + 1) + i];
-            } else {
-                for (uint32_t w = 0; w < HC_MAX; ++w)
-                    if (w < HC) sacc += hist[w * R * (L + 1) + i];
+                    for (uint32_t w = 0; w < 4; ++w)
+                        if (w < HC) sacc += hist[w * R * (L + 1) + i];
+                } else {
+                    for (uint32_t w = 0; w < HC_MAX; ++w)
+                        if (w < HC) sacc += hist[w * R * (L + 1) + i];
+                }
+                hist[i] = sacc;
             }
-            hist[i] = sacc;
-        }
-        __syncthreads();
-        // suffix sums per repetition (one wavefront per repetition, 4 levels
-        // per lane): hist[r][v] = cells of repetition r with count >= v
-        if (sparse) {
-            for (uint32_t r = tid; r < R; r += QT) hist[r * (L + 1)] = B;
-        } else
-        for (uint32_t r = wave; r < R; r += QW) {
-            uint32_t *h = hist + r * (L + 1);
-            uint32_t v[4], loc = 0;
+            __syncthreads();
+            // suffix sums (one wavefront per repetition, 4 levels per lane)
+            for (uint32_t r = wave; r < R; r += QW) {
+                uint32_t *h = hist + r * (L + 1);
+                uint32_t v[4], loc = 0;
 #pragma unroll
-            for (int j = 3; j >= 0; --j) {
-                const uint32_t idx = 4 * lane + j;
-                v[j] = (idx <= L && idx >= 1) ? h[idx] : 0u;
-                loc += v[j];
-                v[j] = loc;  // suffix within the lane's 4 levels
-            }
-            uint32_t above = loc;  // inclusive suffix over lanes >= lane
+                for (int j = 3; j >= 0; --j) {
+                    const uint32_t idx = 4 * lane + j;
+                    v[j] = (idx <= L && idx >= 1) ? h[idx] : 0u;
+                    loc += v[j];
+                    v[j] = loc;  // suffix within the lane's 4 levels
+                }
+                uint32_t above = loc;  // inclusive suffix over lanes >= lane
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = (uint32_t)__shfl_down((int)above, o, 64);
-                if (lane + o < 64) above += y;
-            }
-            const uint32_t after = above - loc;  // lanes > lane
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = (uint32_t)__shfl_down((int)above, o, 64);
+                    if (lane + o < 64) above += y;
+                }
+                const uint32_t after = above - loc;  // lanes > lane
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t idx = 4 * lane + j;
-                if (idx <= L && idx >= 1) h[idx] = v[j] + after;
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t idx = 4 * lane + j;
+                    if (idx <= L && idx >= 1) h[idx] = v[j] + after;
+                }
+                if (lane == 0) h[0] = B;
             }
-            if (lane == 0) h[0] = B;
         }
         __syncthreads();
         // ms[t] = min over repetitions of cells with count >= t (the list
@@ -685,7 +682,6 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         }
         if (tid == 0) {
             misc[M_NEXT] = 0;
-            misc[M_DONE] = 0;
             misc[M_THI] = 0;
         }
         __syncthreads();
@@ -978,7 +974,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                         if (osc) osc[j] = 0u;
                     }
                 }
-                if (tid == 0) misc[M_DONE] = 1;
+                break;  // the decision is the same in every thread
             } else {
                 // lower the level: the lowest level whose cheapest enumeration
                 // stays within 8x the larger of the budget and this pass
@@ -999,7 +995,6 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
             }
             __syncthreads();
-            if (misc[M_DONE]) break;
         }
         if (A.stats && tid == 0) {
             unsigned long long entries = 0;
@@ -1010,8 +1005,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             atomicAdd(&A.stats[3], (unsigned long long)misc[M_ST_PASSES]);
             atomicAdd(&A.stats[4], (unsigned long long)misc[M_ST_FINAL]);
         }
-        __syncthreads();
         if constexpr (!PERS) break;
+        __syncthreads();  // before the next query reuses the LDS state
     }
 }
 

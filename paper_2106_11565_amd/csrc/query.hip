@@ -258,10 +258,10 @@ __device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
 // places taken form a lane mask and each place notes its candidate.  Then
 // each lane pulls its new entry: the candidate's key, or the list entry
 // shifted up by the candidates placed before it.
-__device__ inline void wave_insert(WaveState &ws, uint64_t key, unsigned long long tk, uint32_t k,
+__device__ inline bool wave_insert(WaveState &ws, uint64_t key, unsigned long long tk, uint32_t k,
                                    int lane) {
     const unsigned long long cm = __ballot(key < ws.kth) & tk;
-    if (!cm) return;
+    if (!cm) return false;
     const bool in = __builtin_amdgcn_inverse_ballot_w64(cm);
     if (bcast64(ws.wl, 0) == ~0ull) {
         // empty list (keys never equal ~0: their cell field is below 2^24 - 1)
@@ -285,7 +285,7 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, unsigned long lo
             ws.wl = ((uint32_t)lane < (c < k ? c : k)) ? (((uint64_t)hi << 32) | lo) : ~0ull;
         }
         ws.kth = bcast64(ws.wl, (int)k - 1);
-        return;
+        return true;
     }
     unsigned long long placed = 0;  // list places taken by candidates
     int from = 0;                   // the candidate lane placed at this place
@@ -311,6 +311,15 @@ __device__ inline void wave_insert(WaveState &ws, uint64_t key, unsigned long lo
     const uint64_t v = fromc ? (((uint64_t)chi << 32) | clo) : (((uint64_t)lhi << 32) | llo);
     ws.wl = ((uint32_t)lane < k) ? v : ~0ull;
     ws.kth = bcast64(ws.wl, (int)k - 1);
+    return true;
+}
+
+// Compare-exchange of two keys held by the same lane (ascending).
+__device__ inline void ce64(uint64_t &a, uint64_t &b) {
+    const bool sw = b < a;
+    const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+    a = lo;
+    b = hi;
 }
 
 // Load the group rows of 4 consecutive member slots (4*RP uint16, 16-byte
@@ -387,13 +396,13 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
 #pragma unroll
         for (int g = 0; g < U; ++g) {
             const uint32_t xs[4] = {idv[g].x, idv[g].y, idv[g].z, idv[g].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const bool val = (uint32_t)e < nv[g];
-                // t = (m << 24) | (0xFFFFFF - c*): the minimum over the
-                // member's cells of (count, 0xFFFFFF - cell) is the smallest
-                // count and, among equal counts, the largest cell id (cell
-                // ids stay below 2^24: the counters of all cells fit in LDS)
+            // key of member e of this lane and the lane mask of the kept
+            // members: t = (m << 24) | (0xFFFFFF - c*) is the minimum over the
+            // member's cells of (count, 0xFFFFFF - cell), i.e. the smallest
+            // count and, among equal counts, the largest cell id (cell ids
+            // stay below 2^24: the counters of all cells fit in LDS); the key's
+            // high word is ~t = ((255 - m) << 24) | c*
+            auto member_key = [&](int e, unsigned long long &tm) -> uint64_t {
                 uint32_t t = 0xFFFFFFFFu;
 #pragma unroll
                 for (int r = 0; r < RP; ++r) {
@@ -404,14 +413,40 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
                 }
                 // lane masks of the valid members, of those with m >= level,
                 // and of those kept
-                const unsigned long long vm = __ballot(val);
+                const unsigned long long vm = __ballot((uint32_t)e < nv[g]);
                 const unsigned long long gm = __ballot(t >= (level << 24)) & vm;
-                const unsigned long long tm = keep ? vm : gm;
+                tm = keep ? vm : gm;
                 ws.n_ge += (uint32_t)__popcll(gm);
                 ws.n_all += (uint32_t)__popcll(tm);
-                // high word ~t = ((255 - m) << 24) | c*
-                const uint64_t key = ((uint64_t)(~t) << 32) | xs[e];
-                wave_insert(ws, key, tm, k, lane);
+                return ((uint64_t)(~t) << 32) | xs[e];
+            };
+            if (keep) {
+                // every valid member is kept: each lane's keys in ascending
+                // order (~0, which no key equals, for the invalid ones), so
+                // that the e-th batch holds every lane's e-th smallest key and
+                // once a batch has no candidate the later ones have none
+                uint64_t kv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    unsigned long long tm;
+                    const uint64_t key = member_key(e, tm);
+                    kv[e] = __builtin_amdgcn_inverse_ballot_w64(tm) ? key : ~0ull;
+                }
+                ce64(kv[0], kv[1]);
+                ce64(kv[2], kv[3]);
+                ce64(kv[0], kv[2]);
+                ce64(kv[1], kv[3]);
+                ce64(kv[1], kv[2]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (!wave_insert(ws, kv[e], __ballot(kv[e] != ~0ull), k, lane)) break;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    unsigned long long tm;
+                    const uint64_t key = member_key(e, tm);
+                    wave_insert(ws, key, tm, k, lane);
+                }
             }
         }
     }

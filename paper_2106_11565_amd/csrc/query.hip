@@ -71,8 +71,8 @@ struct QArgs {
 
 struct QLayout {
     uint32_t cnt_words, hist_words, cap;
-    size_t off_cnt, off_hist, off_pre, off_start, off_end, off_buf, off_lb, off_lp, off_tl, off_misc,
-        total;
+    size_t off_cnt, off_hist, off_pre, off_pree, off_start, off_end, off_buf, off_lb, off_lp, off_tl,
+        off_misc, total;
 };
 
 // gk: the general-k decode, which also needs the per-thread prefix slots.
@@ -86,6 +86,7 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned first
     l.off_cnt = o;   o += (size_t)l.cnt_words * 4;
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
+    l.off_pree = o;  o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
     l.off_end = o;   o += (size_t)L * 4;
     l.off_lb = o;    o += cl_for(T) * 4;
@@ -485,6 +486,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
     const uint8_t *cnt8 = lds + lay.off_cnt;
     uint32_t *hist = reinterpret_cast<uint32_t *>(lds + lay.off_hist);
     uint32_t *pre = reinterpret_cast<uint32_t *>(lds + lay.off_pre);
+    uint32_t *pree = reinterpret_cast<uint32_t *>(lds + lay.off_pree);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(lds + lay.off_start);
     uint32_t *lend = reinterpret_cast<uint32_t *>(lds + lay.off_end);
     uint32_t *lb = reinterpret_cast<uint32_t *>(lds + lay.off_lb);
@@ -530,49 +532,86 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
         if (tid == 0) misc[M_NT] = 0;
         if (en > st) nch = (en + CE - 1) / CE - st / CE;
-        uint32_t total;  // chunks over all tables
+        const uint32_t ne = en - st;  // entries
+        uint32_t total, nent;  // chunks and entries over all tables
         if (L <= 64) {
-            // the tables fit in wavefront 0: the scan stays in it
+            // the tables fit in wavefront 0: the scans stay in it
             if (wave == 0) {
-                uint32_t inc = nch;
+                uint32_t inc = nch, ince = ne;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
                     const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
-                    if (lane >= o) inc += y;
+                    const uint32_t ye = (uint32_t)__shfl_up((int)ince, o, 64);
+                    if (lane >= o) {
+                        inc += y;
+                        ince += ye;
+                    }
                 }
                 if ((uint32_t)lane < L) {
                     pre[lane] = inc - nch;
+                    pree[lane] = ince - ne;
                     lstart[lane] = st;
                     lend[lane] = en;
                 }
-                if (lane == 63) pre[L] = inc;  // lanes past L add nothing
+                if (lane == 63) {  // lanes past L add nothing
+                    pre[L] = inc;
+                    pree[L] = ince;
+                }
             }
             __syncthreads();
             total = pre[L];
+            nent = pree[L];
         } else {
             const uint32_t ex = wg_excl_scan<QT>(nch, scr, &total);
+            const uint32_t exe = wg_excl_scan<QT>(ne, scr, &nent);
             if ((uint32_t)tid < L) {
                 pre[tid] = ex;
+                pree[tid] = exe;
                 lstart[tid] = st;
                 lend[tid] = en;
             }
-            if (tid == 0) pre[L] = total;
+            if (tid == 0) {
+                pre[L] = total;
+                pree[L] = nent;
+            }
             __syncthreads();
         }
 
-        // ---- 2. count: one increment per listed cell per table.  Chunk ci
-        // belongs to the last table t with pre[t] <= ci; a thread's chunks
-        // only grow, so after one binary search its table index only moves
-        // forward.  Four aligned 16-byte chunks per thread are loaded before
-        // their increments; entries outside the table's list are skipped.
-        // With few entries for the number of cells (sparse), each increment
-        // also adds one to the count-at-least histogram of the cell's
-        // repetition at the new count (the old count comes back from the
-        // atomic), which replaces the scan of all counters below.
-        const bool sparse = (uint64_t)total * CE <= lay.cnt_words;
+        // ---- 2. count: one increment per listed cell per table.
+        // Dense (many entries for the number of cells): chunk ci belongs to
+        // the last table t with pre[t] <= ci; a thread's chunks only grow, so
+        // after one binary search its table index only moves forward.  Four
+        // aligned 16-byte chunks per thread are loaded before their
+        // increments; entries outside the table's list are skipped.
+        // Sparse: one entry per thread (entry j in the last table t with
+        // pre_e[t] <= j), and each increment also adds one to the
+        // count-at-least histogram of the cell's repetition at the new count
+        // (the old count comes back from the atomic), which replaces the
+        // scan of all counters below; a cell's first increment notes it.
+        const bool sparse = nent <= lay.cnt_words;
         // (the sparse increments are few: one copy takes them all)
         uint32_t *hwc = hist + (sparse ? 0u : ((uint32_t)tid & (HC - 1)) * R * (L + 1));
-        {
+        if (sparse) {
+            for (uint32_t j = tid; j < nent; j += QT) {
+                uint32_t lo = 0, hi = L;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (pree[mid] <= j) lo = mid; else hi = mid;
+                }
+                const uint32_t c = cells[lstart[lo] + (j - pree[lo])];
+                const uint32_t sh = 8 * (c & 3);
+                const uint32_t old = atomicAdd(&cnt32[c >> 2], 1u << sh);
+                const uint32_t ob = (old >> sh) & 255u;
+                const uint32_t r = div_small(c, Bp, A.inv_bp);
+                atomicAdd(&hwc[r * (L + 1) + ob + 1], 1u);
+                if constexpr (!GK) {
+                    if (ob == 0) {
+                        const uint32_t slot = atomicAdd(&misc[M_NT], 1u);
+                        if (slot < TLC) tl[slot] = c;
+                    }
+                }
+            }
+        } else {
             const uint4 *cells16 = static_cast<const uint4 *>(A.cells);
             uint32_t t = 0;
             if ((uint32_t)tid < total) {
@@ -610,24 +649,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                         const uint32_t j = chunk[u] * CE + e;
                         const uint32_t c = (CE == 8) ? ((w4[e / 2] >> (16 * (e & 1))) & 0xFFFFu)
                                                      : w4[e % 4];
-                        if (j >= lo && j < hi) {
-                            const uint32_t sh = 8 * (c & 3);
-                            if (sparse) {
-                                const uint32_t old = atomicAdd(&cnt32[c >> 2], 1u << sh);
-                                const uint32_t ob = (old >> sh) & 255u;
-                                const uint32_t r = div_small(c, Bp, A.inv_bp);
-                                atomicAdd(&hwc[r * (L + 1) + ob + 1], 1u);
-                                if constexpr (!GK) {
-                                    // first hit of the cell: note it
-                                    if (ob == 0) {
-                                        const uint32_t slot = atomicAdd(&misc[M_NT], 1u);
-                                        if (slot < TLC) tl[slot] = c;
-                                    }
-                                }
-                            } else {
-                                atomicAdd(&cnt32[c >> 2], 1u << sh);
-                            }
-                        }
+                        if (j >= lo && j < hi) atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
                     }
                 }
             }

@@ -104,6 +104,8 @@ static flinng_input slice(const flinng_input &in, const Index &ix, uint64_t begi
 static void free_index(Index *ix) {
     if (!ix) return;
     (void)hipSetDevice(ix->device);
+    for (auto &e : ix->scratch)
+        if (e.ptr) (void)hipFree(e.ptr);
     if (ix->offsets) (void)hipFree(ix->offsets);
     if (ix->cells) (void)hipFree(ix->cells);
     if (ix->grp) (void)hipFree(ix->grp);
@@ -218,6 +220,40 @@ int flinng_index_get_info(const flinng_index *idx, flinng_index_info *info) {
     });
 }
 
+// The index's codes region for stream s, at least `bytes` long (see
+// Index::scratch), with ix.scratch_mu held by the caller until the work that
+// uses it is queued (two threads queueing on one stream must not interleave
+// their hash and query launches).  At most 8 streams are remembered; the
+// oldest is evicted.
+static uint32_t *codes_scratch(const Index &ix, hipStream_t s, size_t bytes) {
+    Index::StreamScratch *slot = nullptr;
+    for (auto &e : ix.scratch)
+        if (e.stream == s) slot = &e;
+    if (slot && slot->cap >= bytes) return static_cast<uint32_t *>(slot->ptr);
+    if (!slot) {
+        if (ix.scratch.size() >= 8) {
+            if (ix.scratch.front().ptr) (void)hipFree(ix.scratch.front().ptr);
+            ix.scratch.erase(ix.scratch.begin());
+        }
+        ix.scratch.push_back({s, nullptr, 0});
+        slot = &ix.scratch.back();
+    }
+    if (slot->ptr) (void)hipFree(slot->ptr);  // waits for the work using it
+    slot->ptr = nullptr;
+    slot->cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64 * 1024);
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? FLINNG_ENOMEM : FLINNG_EDEVICE,
+             "device allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    slot->ptr = p;
+    slot->cap = cap;
+    return static_cast<uint32_t *>(p);
+}
+
 int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uint32_t *ids,
                  uint32_t *scores, uint32_t out_on_device, uint32_t persistent, void *stream) {
     return guard([&] {
@@ -230,17 +266,18 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uin
         if (nq == 0) return;
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
-        DevBuf codes(nq * ix.p.L * 4, s);
-        hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        std::unique_lock<std::mutex> lock(ix.scratch_mu);
+        uint32_t *codes = codes_scratch(ix, s, (size_t)nq * ix.p.L * 4);
+        hash_batch(ix, *q, codes, s, nullptr);
         DevBuf work(persistent ? 4 : 0, s);
         if (out_on_device) {
-            query_launch(ix, codes.as<uint32_t>(), nq, k, ids, scores, persistent != 0, s,
-                         work.as<uint32_t>());
+            query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>());
+            lock.unlock();
         } else {
             DevBuf dids(nq * k * 4, s), dsc(scores ? nq * k * 4 : 0, s);
-            query_launch(ix, codes.as<uint32_t>(), nq, k, dids.as<uint32_t>(),
-                         scores ? dsc.as<uint32_t>() : nullptr, persistent != 0, s,
-                         work.as<uint32_t>());
+            query_launch(ix, codes, nq, k, dids.as<uint32_t>(), scores ? dsc.as<uint32_t>() : nullptr,
+                         persistent != 0, s, work.as<uint32_t>());
+            lock.unlock();
             FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
             if (scores) FL_HIP(hipMemcpyAsync(scores, dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
             FL_HIP(hipStreamSynchronize(s));

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,17 @@ struct Index {
     uint16_t *cmg = nullptr;
     uint16_t *hyp = nullptr;
     float *hypnorm = nullptr;
+    // Device scratch for the codes of one query batch, one region per
+    // stream the index is queried on: work on one stream runs in order, so
+    // a region is reused without waiting.  Grown (and evicted) with a
+    // synchronous free; released with the index.
+    struct StreamScratch {
+        hipStream_t stream;
+        void *ptr;
+        size_t cap;
+    };
+    mutable std::mutex scratch_mu;
+    mutable std::vector<StreamScratch> scratch;
 };
 
 inline uint64_t nbuckets(const Index &ix) { return 1ull << ix.nbits; }

@@ -2,10 +2,10 @@
 //
 // One workgroup owns one query at a time (a persistent grid pulls queries
 // from a device counter).  All per-query state lives in LDS:
-//   * the B*R cell counters as bytes (count <= L <= 255), 4 per dword,
-//     incremented with 32-bit LDS atomics while the workgroup walks the L
-//     reverse-index lists selected by the query's codes (Section 6: count how
-//     often each cell collides with the query);
+//   * the B*R cell counters as bytes, 4 per dword, holding 255 - count
+//     (count <= L <= 255), decremented with 32-bit LDS atomics while the
+//     workgroup walks the L reverse-index lists selected by the query's codes
+//     (Section 6: count how often each cell collides with the query);
 //   * per-repetition histograms of the nonzero counts;
 //   * a list of positive cells and a top-k key buffer.
 // Decode (Algorithm 3, threshold relaxation).  Walking cells by descending
@@ -83,8 +83,8 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.hist_words = hc * R * (L + 1);
     l.cap = cap;
     size_t o = 0;
-    l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned first
-    l.off_cnt = o;   o += (size_t)l.cnt_words * 4;
+    l.off_cnt = o;   o += (size_t)l.cnt_words * 4;  // first: a counter's LDS address is its cell id
+    l.off_buf = o;   o += (size_t)cap * 8;          // 8-byte aligned (16-byte counter units)
     l.off_pre = o;   o += (size_t)(L + 1) * 4;
     l.off_pree = o;  o += (size_t)(L + 1) * 4;
     l.off_start = o; o += (size_t)L * 4;
@@ -349,6 +349,15 @@ __device__ inline uint32_t row_group(const uint32_t (&w)[2 * RP], int e, int r) 
     return (w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
 }
 
+// A byte of LDS by its address.  The query kernel uses no static LDS, so its
+// dynamic LDS (where the counters come first) starts at address 0 and the
+// counter of cell c sits at address c (the launcher checks that the kernel
+// has no static LDS).
+typedef __attribute__((address_space(3))) const uint8_t lds_byte;
+__device__ inline uint32_t lds_u8_at(uint32_t addr) {
+    return *reinterpret_cast<lds_byte *>((size_t)addr);
+}
+
 // Stream the members of the cells lbs[0, nl) of one repetition: for each
 // member, its id and its group row give m and c* from the LDS counters; keys
 // with m >= level (all keys when `keep`) go into the wavefront's top-k.
@@ -388,38 +397,36 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
         }
         // repetition r's counters start at rb[r]; the padding repetitions
         // r >= R repeat repetition R-1 (its group is repeated in the rows)
-        uint32_t rb[RP], xr[RP];
+        uint32_t rb[RP];
 #pragma unroll
-        for (int r = 0; r < RP; ++r) {
-            rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
-            xr[r] = 0xFFFFFFu - rb[r];
-        }
+        for (int r = 0; r < RP; ++r) rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
 #pragma unroll
         for (int g = 0; g < U; ++g) {
             const uint32_t xs[4] = {idv[g].x, idv[g].y, idv[g].z, idv[g].w};
             // key of member e of this lane and the lane mask of the kept
-            // members: t = (m << 24) | (0xFFFFFF - c*) is the minimum over the
-            // member's cells of (count, 0xFFFFFF - cell), i.e. the smallest
-            // count and, among equal counts, the largest cell id (cell ids
-            // stay below 2^24: the counters of all cells fit in LDS); the key's
-            // high word is ~t = ((255 - m) << 24) | c*
+            // members.  The counters hold 255 - count at LDS byte address =
+            // cell id, so t = max over the member's cells of
+            // ((255 - count) << 24 | cell) is the key's high word
+            // ((255 - m) << 24) | c*: the smallest count and, among equal
+            // counts, the largest cell id (cell ids stay below 2^24: the
+            // counters of all cells fit in LDS).  m >= level iff
+            // t < (256 - level) << 24 (level >= 1).
             auto member_key = [&](int e, unsigned long long &tm) -> uint64_t {
-                uint32_t t = 0xFFFFFFFFu;
+                uint32_t t = 0;
 #pragma unroll
                 for (int r = 0; r < RP; ++r) {
-                    const uint32_t gr = row_group<RP>(rows[g], e, r);
-                    const uint32_t v = cnt8[rb[r] + gr];
-                    const uint32_t tv = (v << 24) | (xr[r] - gr);
-                    t = tv < t ? tv : t;
+                    const uint32_t c = rb[r] + row_group<RP>(rows[g], e, r);
+                    const uint32_t tv = (lds_u8_at(c) << 24) | c;
+                    t = tv > t ? tv : t;
                 }
                 // lane masks of the valid members, of those with m >= level,
                 // and of those kept
                 const unsigned long long vm = __ballot((uint32_t)e < nv[g]);
-                const unsigned long long gm = __ballot(t >= (level << 24)) & vm;
+                const unsigned long long gm = __ballot(t < ((256u - level) << 24)) & vm;
                 tm = keep ? vm : gm;
                 ws.n_ge += (uint32_t)__popcll(gm);
                 ws.n_all += (uint32_t)__popcll(tm);
-                return ((uint64_t)(~t) << 32) | xs[e];
+                return ((uint64_t)t << 32) | xs[e];
             };
             if (keep) {
                 // every valid member is kept: each lane's keys in ascending
@@ -460,7 +467,7 @@ __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t B
     cs = 0;
     for (uint32_t r = 0; r < R; ++r) {
         const uint32_t c = r * Bp + row[r];
-        const uint32_t v = cnt8[c];
+        const uint32_t v = 255u - cnt8[c];
         if (v <= m) {
             m = v;
             cs = c;
@@ -527,7 +534,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         }
         {
             uint4 *c16 = reinterpret_cast<uint4 *>(cnt32);
-            for (uint32_t w = tid; w < lay.cnt_words / 4; w += QT) c16[w] = make_uint4(0, 0, 0, 0);
+            for (uint32_t w = tid; w < lay.cnt_words / 4; w += QT)
+                c16[w] = make_uint4(~0u, ~0u, ~0u, ~0u);  // count 0
         }
         for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
         if (tid == 0) misc[M_NT] = 0;
@@ -600,8 +608,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
                 const uint32_t c = cells[lstart[lo] + (j - pree[lo])];
                 const uint32_t sh = 8 * (c & 3);
-                const uint32_t old = atomicAdd(&cnt32[c >> 2], 1u << sh);
-                const uint32_t ob = (old >> sh) & 255u;
+                const uint32_t old = atomicSub(&cnt32[c >> 2], 1u << sh);
+                const uint32_t ob = 255u - ((old >> sh) & 255u);  // count before
                 const uint32_t r = div_small(c, Bp, A.inv_bp);
                 atomicAdd(&hwc[r * (L + 1) + ob + 1], 1u);
                 if constexpr (!GK) {
@@ -649,7 +657,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                         const uint32_t j = chunk[u] * CE + e;
                         const uint32_t c = (CE == 8) ? ((w4[e / 2] >> (16 * (e & 1))) & 0xFFFFu)
                                                      : w4[e % 4];
-                        if (j >= lo && j < hi) atomicAdd(&cnt32[c >> 2], 1u << (8 * (c & 3)));
+                        if (j >= lo && j < hi) atomicSub(&cnt32[c >> 2], 1u << (8 * (c & 3)));
                     }
                 }
             }
@@ -659,7 +667,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         if (A.counts_out) {
             // debug: export counters as [R][B] bytes
             uint8_t *out = A.counts_out + q * (uint64_t)R * B;
-            for (uint32_t c = tid; c < R * B; c += QT) out[c] = cnt8[(c / B) * Bp + c % B];
+            for (uint32_t c = tid; c < R * B; c += QT) out[c] = 255u - cnt8[(c / B) * Bp + c % B];
             __syncthreads();
             if constexpr (!PERS) break;
             continue;
@@ -673,7 +681,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             for (uint32_t r = tid; r < R; r += QT) hist[r * (L + 1)] = B;
         } else {
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
-                const uint32_t v = cnt32[w];
+                const uint32_t v = ~cnt32[w];  // four counts
                 if (!v) continue;
                 const uint32_t r = div_small(4 * w, Bp, A.inv_bp);
 #pragma unroll
@@ -830,11 +838,11 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     const uint32_t c0 = rep * Bp;
                     for (uint32_t i = tid; i < nt; i += QT) {
                         const uint32_t c = tl[i];
-                        if (c - c0 < B && cnt8[c] >= level) lb[atomicAdd(&misc[M_LCNT], 1u)] = c - c0;
+                        if (c - c0 < B && 255u - cnt8[c] >= level) lb[atomicAdd(&misc[M_LCNT], 1u)] = c - c0;
                     }
                 } else {
                     for (uint32_t w = tid; w < Bp / 4; w += QT) {
-                        const uint32_t v = cnt32[rep * (Bp / 4) + w];
+                        const uint32_t v = ~cnt32[rep * (Bp / 4) + w];  // four counts
                         if (!v) continue;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
@@ -851,7 +859,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
                 for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
                     const uint32_t b = cb0 + tid;
-                    const bool pos = (b < B) && (cnt8[rep * Bp + b] >= level);
+                    const bool pos = (b < B) && (255u - cnt8[rep * Bp + b] >= level);
                     const unsigned long long pm = __ballot(pos);
                     uint32_t wbase = 0;
                     if (lane == 0 && pm) wbase = atomicAdd(&misc[M_LCNT], (uint32_t)__popcll(pm));
@@ -910,7 +918,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
                 const uint32_t b = cb0 + tid;
                 uint32_t cval = 0;
-                if (b < B) cval = cnt8[rep * Bp + b];
+                if (b < B) cval = 255u - cnt8[rep * Bp + b];
                 const bool pos = (b < B) && (cval >= level);
                 const uint32_t sz = pos ? (q0 + (b < rem ? 1u : 0u)) : 0u;
                 uint32_t npos, tsz;
@@ -1010,7 +1018,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     const uint32_t *memz = A.mem + (R - 1) * rstride;
                     for (uint32_t b0 = 0; b0 < B && need; b0 += 64) {
                         const uint32_t b = b0 + lane;
-                        const bool z = (b < B) && (cnt8[(R - 1) * Bp + b] == 0);
+                        const bool z = (b < B) && (cnt8[(R - 1) * Bp + b] == 255u);  // count 0
                         unsigned long long zm = __ballot(z);
                         while (zm && need) {
                             const uint32_t bb = b0 + (uint32_t)(__ffsll((long long)zm) - 1);
@@ -1152,9 +1160,12 @@ template <typename CellT, int RP, int QT, bool GK, bool PERS, int WAVES>
 static void launch_kernel(const QArgs &a, size_t lds, unsigned grid, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK, PERS, WAVES>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
+        const void *fn = reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK, PERS, WAVES>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
+        // the counters are addressed from LDS address 0 (dynamic LDS first)
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes != 0)
+            fail(FLINNG_EDEVICE, "query kernel: static LDS in use or attributes unavailable");
         attr_set = true;
     }
     hipLaunchKernelGGL((query_kernel<CellT, RP, QT, GK, PERS, WAVES>), dim3(grid), dim3(QT), lds, s, a);

@@ -538,7 +538,11 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 c16[w] = make_uint4(~0u, ~0u, ~0u, ~0u);  // count 0
         }
         for (uint32_t w = tid; w < lay.hist_words; w += QT) hist[w] = 0u;
-        if (tid == 0) misc[M_NT] = 0;
+        if (tid == 0) {
+            misc[M_NT] = 0;
+            misc[M_THI] = 0;
+            misc[M_NEXT] = 0;
+        }
         if (en > st) nch = (en + CE - 1) / CE - st / CE;
         const uint32_t ne = en - st;  // entries
         uint32_t total, nent;  // chunks and entries over all tables
@@ -674,12 +678,10 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         }
 
         // ---- 3. per-repetition histograms, as counts-at-least: hist[r][v] =
-        // cells of repetition r with count >= v (sparse: built while
-        // counting; dense: a scan of the counters into HC copies, the copies
-        // merged, then suffix sums)
-        if (sparse) {
-            for (uint32_t r = tid; r < R; r += QT) hist[r * (L + 1)] = B;
-        } else {
+        // cells of repetition r with count >= v for v >= 1 (sparse: built
+        // while counting; dense: a scan of the counters into HC copies, the
+        // copies merged, then suffix sums)
+        if (!sparse) {
             for (uint32_t w = tid; w < lay.cnt_words; w += QT) {
                 const uint32_t v = ~cnt32[w];  // four counts
                 if (!v) continue;
@@ -730,46 +732,47 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
                 if (lane == 0) h[0] = B;
             }
+            __syncthreads();
         }
-        __syncthreads();
         // ms[t] = min over repetitions of cells with count >= t (the list
         // offsets are no longer needed, so `pre` holds it).  Enumerating the
         // level-t cells of the cheapest repetition reads about ms[t]*ceil(N/B)
-        // members; ms is non-increasing in t.
-        uint32_t *ms = pre;
-        for (uint32_t t = tid; t <= L; t += QT) {
-            uint32_t mn = 0xFFFFFFFFu;
-            for (uint32_t r = 0; r < R; ++r) {
-                const uint32_t c = hist[r * (L + 1) + t];
-                mn = c < mn ? c : mn;
-            }
-            ms[t] = mn;
-        }
-        if (tid == 0) {
-            misc[M_NEXT] = 0;
-            misc[M_THI] = 0;
-        }
-        __syncthreads();
+        // members; ms is non-increasing in t.  Level t belongs to thread
+        // t - 1 (L < QT), here and when the level is lowered.
         // t_hi = #{t in 1..L : ms[t]*gmax >= k} (a prefix of levels);
         // t_lo = #{t in 1..L : ms[t]*gmax <= budget} (a suffix of levels).
-        // (level t is thread t - 1's: L < QT)
+        uint32_t *ms = pre;
         {
             const uint32_t t = 1 + tid;
-            const uint64_t sz = (t <= L) ? (uint64_t)ms[t] * gmax : 0;
+            uint64_t sz = 0;
+            if (t <= L) {
+                uint32_t mn = 0xFFFFFFFFu;
+                for (uint32_t r = 0; r < R; ++r) {
+                    const uint32_t c = hist[r * (L + 1) + t];
+                    mn = c < mn ? c : mn;
+                }
+                ms[t] = mn;
+                sz = (uint64_t)mn * gmax;
+            }
             const unsigned long long mh = __ballot(t <= L && sz >= k);
             const unsigned long long ml = __ballot(t <= L && sz <= A.budget);
-            if (lane == 0 && (uint32_t)wave * 64 < L) {
-                atomicAdd(&misc[M_THI], (uint32_t)__popcll(mh));
-                atomicAdd(&misc[M_NEXT], (uint32_t)__popcll(ml));
+            uint32_t thi = 0, tlo = 0;
+            if (L <= 64) {
+                // every level is in wavefront 0
+                thi = (uint32_t)__popcll(mh);
+                tlo = L + 1 - (uint32_t)__popcll(ml);
+            } else {
+                if (lane == 0 && (uint32_t)wave * 64 < L) {
+                    atomicAdd(&misc[M_THI], (uint32_t)__popcll(mh));
+                    atomicAdd(&misc[M_NEXT], (uint32_t)__popcll(ml));
+                }
+                __syncthreads();
+                thi = misc[M_THI];
+                tlo = L + 1 - misc[M_NEXT];
             }
+            // the lowest level within the budget, but at most t_hi
+            if (tid == 0) misc[M_LEVEL] = (thi == 0) ? 0u : (tlo <= thi ? tlo : thi);
         }
-        __syncthreads();
-        if (tid == 0) {
-            const uint32_t thi = misc[M_THI];
-            const uint32_t tlo = L + 1 - misc[M_NEXT];  // lowest level within the budget
-            misc[M_LEVEL] = (thi == 0) ? 0u : (tlo <= thi ? tlo : thi);
-        }
-        __syncthreads();
 
         // ---- 4. decode passes
         // per-query work tallies (members read, in the final pass, passes) in
@@ -887,10 +890,15 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             }
             __syncthreads();
             if (QW * k <= 64) {
-                if (wave == 0) {
+                // only a final pass needs the result, and then wavefront 0
+                // alone emits it (lane i writes and reads entry i): the other
+                // wavefronts are done
+                const bool fin = misc[M_NGE] >= k || keep;
+                if (fin && wave == 0) {
                     const uint64_t v = wave_sort64((uint32_t)lane < QW * k ? wlist[lane] : ~0ull, lane);
                     if ((uint32_t)lane < k) buf[lane] = v;
                 }
+                if (fin && wave != 0) break;
             } else if ((uint32_t)tid < QW * k) {
                 const uint32_t w = tid / k, i = tid % k;
                 const uint64_t key = wlist[w * k + i];
@@ -908,7 +916,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     if (rank < k) buf[rank] = key;
                 }
             }
-            __syncthreads();
+            if (QW * k > 64) __syncthreads();
           } else {
             // General k: cells 256 at a time, candidates appended to a
             // capacity-cap LDS buffer under a tightening threshold; the

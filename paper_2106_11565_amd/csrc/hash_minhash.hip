@@ -9,11 +9,11 @@
 //   h = sm64(key_MH, L*K + t); for j < K: h = splitmix_finalize(h XOR mh_tj)
 //   bucket_t = h >> (64 - bucket_bits)
 //
-// Mapping: one wavefront per set.  The 64 lanes are F = 64/S hash functions
-// times S item slices; lane (f, s) takes the minimum over items s, s+S, ...
-// of its function, then the S partial minima of each function are combined
-// by a wavefront integer min-reduction (cross-lane shuffles).  S is chosen
-// per batch from the mean set size so that the lanes stay busy.
+// Mapping: one wavefront per set.  The 64 lanes are F = floor(64/S) hash
+// functions times S item slices; lane (f, s) takes the minimum over items s,
+// s+S, ... of its function, then the S partial minima of each function are
+// combined by LDS atomic minima.  S (any count up to 16) is chosen per batch
+// from the mean set size so that the lanes stay busy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,10 +23,10 @@
 
 namespace flinng {
 
-template <int S, typename ItemT>
+template <typename ItemT>
 __global__ __launch_bounds__(256) void minhash_kernel(
     const ItemT *__restrict__ items, const uint64_t *__restrict__ offsets, uint64_t nsets,
-    uint32_t K, uint32_t L, uint32_t bbits, uint64_t key, uint32_t *__restrict__ codes) {
+    uint32_t K, uint32_t L, uint32_t bbits, uint64_t key, uint32_t S, uint32_t *__restrict__ codes) {
     extern __shared__ uint32_t mins_all[];
     const int lane = threadIdx.x % 64;
     const int wave = threadIdx.x / 64;
@@ -34,26 +34,25 @@ __global__ __launch_bounds__(256) void minhash_kernel(
     if (set >= nsets) return;
     const uint32_t LK = L * K;
     uint32_t *mins = mins_all + wave * LK;
+    for (uint32_t f = lane; f < LK; f += 64) mins[f] = 0xFFFFFFFFu;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint64_t beg = offsets[set], end = offsets[set + 1];
-    constexpr int F = 64 / S;
-    const int fl = lane / S, sl = lane % S;
+    const uint32_t F = 64 / S;
+    const uint32_t fl = (uint32_t)lane / S, sl = (uint32_t)lane % S;
     for (uint32_t f0 = 0; f0 < LK; f0 += F) {
         const uint32_t fi = f0 + fl;
-        const uint64_t a = sm64(key, fi);
-        uint32_t mn = 0xFFFFFFFFu;
-        if (fi < LK) {
+        if (fl < F && fi < LK) {
+            const uint64_t a = sm64(key, fi);
+            uint32_t mn = 0xFFFFFFFFu;
             for (uint64_t p = beg + sl; p < end; p += S) {
                 const uint64_t e = (uint64_t)items[p];
                 const uint32_t v = (uint32_t)(splitmix_finalize(e ^ a) >> 32);
                 mn = v < mn ? v : mn;
             }
+            atomicMin(&mins[fi], mn);
         }
-#pragma unroll
-        for (int o = 1; o < S; o <<= 1) {
-            const uint32_t other = (uint32_t)__shfl_xor((int)mn, o, 64);
-            mn = other < mn ? other : mn;
-        }
-        if (sl == 0 && fi < LK) mins[fi] = mn;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -65,14 +64,15 @@ __global__ __launch_bounds__(256) void minhash_kernel(
     }
 }
 
-// Slices per function minimising (passes over functions) x (items per lane +
-// reduction steps) for the batch's mean set size.
+// Slices per function minimising (passes over functions) x (items per lane)
+// for the batch's mean set size, plus one atomic minimum per lane and pass.
 static int choose_slices(uint32_t LK, double mean_items) {
     int best = 1;
     double best_cost = 1e300;
-    for (int S = 1; S <= 16; S <<= 1) {
-        double passes = std::ceil((double)LK * S / 64.0);
-        double cost = passes * (std::ceil(mean_items / S) + std::log2((double)S) * 0.75);
+    for (int S = 1; S <= 16; ++S) {
+        const double F = (double)(64 / S);
+        const double passes = std::ceil((double)LK / F);
+        const double cost = passes * (std::ceil(mean_items / S) + 1.0);
         if (cost < best_cost - 1e-9) {
             best_cost = cost;
             best = S;
@@ -87,13 +87,8 @@ static void launch_minhash(int S, const ItemT *items, const uint64_t *offs, uint
                            hipStream_t s) {
     dim3 grid((unsigned)((n + 3) / 4)), block(256);
     size_t lds = 4 * (size_t)L * K * sizeof(uint32_t);
-    switch (S) {
-        case 1: hipLaunchKernelGGL((minhash_kernel<1, ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key, codes); break;
-        case 2: hipLaunchKernelGGL((minhash_kernel<2, ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key, codes); break;
-        case 4: hipLaunchKernelGGL((minhash_kernel<4, ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key, codes); break;
-        case 8: hipLaunchKernelGGL((minhash_kernel<8, ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key, codes); break;
-        default: hipLaunchKernelGGL((minhash_kernel<16, ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key, codes); break;
-    }
+    hipLaunchKernelGGL((minhash_kernel<ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key,
+                       (uint32_t)S, codes);
     FL_CHECK_LAUNCH();
 }
 

@@ -128,8 +128,11 @@ int flinng_build(const flinng_params *p, const flinng_input *data,
  *  persistent  0: one workgroup per query; 1: a persistent grid that pulls
  *           queries from a device counter (for uneven batches in one launch).
  * Device outputs: the call returns once the work is enqueued on `stream`.
- * Host outputs: the call synchronizes `stream`.  The index is read-only, so
- * concurrent calls on different streams are allowed.
+ * Host outputs: the call synchronizes `stream`.  The index data is
+ * read-only, so concurrent calls (from any threads, on any streams) are
+ * allowed.  The batch's codes go to a device region the index keeps for
+ * each stream it is queried on (up to 8 streams; allocated on first use,
+ * grown synchronously for a larger batch, freed by flinng_index_free).
  */
 int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
                  uint32_t *ids, uint32_t *scores, uint32_t out_on_device,

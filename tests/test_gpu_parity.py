@@ -212,3 +212,53 @@ def test_many_positive_cells_chunked(fl, R):
         want = oracle_query(oi, Q, k)
         got = gi.query(Q, k)
         assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), k
+
+
+def test_query_streams_and_threads(fl):
+    """flinng_query keeps one codes region per stream: batches queried from
+    several host threads on several streams (two threads sharing one
+    stream), and a later larger batch that grows a region, give the same
+    ids and scores as the oracle."""
+    import threading
+
+    import torch
+    cfg, (it, of), (qit, qof), _ = scaled("c2", 0.01, 120)
+    gi, oi = build_both(fl, 3, (it, of), cfg["K"], cfg["L"], cfg["R"], cfg["B"], 21,
+                        cfg["bucket_bits"])
+    want_i, want_s = oracle_query(oi, (qit, qof), 10)
+
+    def dev(a):
+        a = np.ascontiguousarray(a)
+        return torch.from_numpy(a.view(np.int64)).cuda()
+
+    q_d = (dev(qit), dev(qof))
+    nq = len(qof) - 1
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()]
+    results, errors = {}, []
+
+    def worker(t, s):
+        try:
+            ids = torch.empty((nq, 10), dtype=torch.int32, device="cuda")
+            sc = torch.empty((nq, 10), dtype=torch.int32, device="cuda")
+            for _ in range(5):
+                gi.query(q_d, 10, stream=s, out=(ids, sc))
+            s.synchronize()
+            results[t] = (ids.cpu().numpy().view(np.uint32), sc.cpu().numpy().view(np.uint32))
+        except Exception as e:  # noqa: BLE001
+            errors.append(repr(e))
+
+    stream_of = [0, 1, 2, 0]  # threads 0 and 3 share a stream
+    threads = [threading.Thread(target=worker, args=(t, streams[stream_of[t]])) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for t, (gi_, gs_) in results.items():
+        assert np.array_equal(gi_, want_i) and np.array_equal(gs_, want_s), t
+    # a larger batch on a stream whose region was sized for the smaller one
+    big_it = np.concatenate([qit, qit])
+    big_of = np.concatenate([qof, qof[1:] + qof[-1]])
+    got_i, got_s = gi.query((dev(big_it), dev(big_of)), 10, stream=streams[0])
+    assert np.array_equal(got_i[:nq], want_i) and np.array_equal(got_i[nq:], want_i)
+    assert np.array_equal(got_s[:nq], want_s) and np.array_equal(got_s[nq:], want_s)

@@ -6,8 +6,9 @@
 //     (count <= L <= 255), decremented with 32-bit LDS atomics while the
 //     workgroup walks the L reverse-index lists selected by the query's codes
 //     (Section 6: count how often each cell collides with the query);
-//   * per-repetition histograms of the nonzero counts;
-//   * a list of positive cells and a top-k key buffer.
+//   * per-repetition histograms of the nonzero counts (as counts-at-least);
+//   * the list of cells the query touched (sparse queries), a list of
+//     positive cells and a top-k key buffer.
 // Decode (Algorithm 3, threshold relaxation).  Walking cells by descending
 // count and reporting a point when all R of its cells have been walked means
 // a point x completes at its last-ranked cell, so the output is the k
@@ -33,10 +34,10 @@ namespace flinng {
 
 // Threads per query workgroup: 256, or 1024 when the per-query LDS state
 // leaves room for only one workgroup per CU (more wavefronts to hide
-// latency).  The count histograms have HC copies (thread t adds to copy
-// t mod HC) so that the many increments of the few low count values do not
-// serialise on one LDS address; HC is a power of two sized to the LDS left
-// over.
+// latency).  Dense queries build the count histograms in HC copies (thread t
+// adds to copy t mod HC) so that the many increments of the few low count
+// values do not serialise on one LDS address; HC is a power of two sized to
+// the LDS left over.
 constexpr uint32_t HC_MAX = 32;
 constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
 // positive-cell list capacity (at least one round of T cells)

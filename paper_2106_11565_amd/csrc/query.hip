@@ -1112,7 +1112,9 @@ struct QShape {
 // budget admits four per CU: 16 wavefronts), else 1024 threads with one
 // workgroup per CU (also 16).  The histogram copies take what the LDS share
 // of one workgroup has left, up to HC_MAX.
-static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
+// sparse: the index's lists are short enough that its queries are expected
+// to count sparsely, with the histogram built while counting (no copies).
+static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k, bool sparse) {
     const size_t lim = (size_t)max_lds();
     const size_t bins = (size_t)R * (L + 1) * 4;
     QShape sh;
@@ -1120,9 +1122,10 @@ static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
     const size_t small = q_layout(L, R, Bp, cap_for(k, 256), 256, 1, gk).total;
     if (small * 4 <= lim) {
         // a state this small holds few cells, so few counts collide: four
-        // copies (more only add clearing and merging)
+        // copies (more only add clearing and merging), none for sparse
+        // queries, whose smaller state may then let one more workgroup in
         sh.T = 256;
-        sh.hc = (uint32_t)std::min<size_t>(4, 1 + (lim / 4 - small) / bins);
+        sh.hc = sparse ? 1u : (uint32_t)std::min<size_t>(4, 1 + (lim / 4 - small) / bins);
     } else {
         const size_t big = q_layout(L, R, Bp, cap_for(k, 1024), 1024, 1, gk).total;
         sh.T = big <= lim ? 1024 : 256;
@@ -1134,9 +1137,18 @@ static QShape q_shape(uint32_t L, uint32_t R, uint32_t Bp, uint32_t k) {
     return sh;
 }
 
+// Whether an index's queries are expected to count sparsely: the mean list
+// entries a query meets (all lists over all buckets) at most a quarter of the
+// counter words (the per-query test is entries <= counter words).
+static bool sparse_index(const Index &ix) {
+    const uint32_t Bp = (ix.p.B + 3) & ~3u;
+    const uint64_t words = ((uint64_t)ix.p.R * Bp) / 4;
+    return (ix.list_entries >> ix.nbits) * 4 <= words;
+}
+
 size_t query_lds_bytes(const Index &ix, uint32_t k) {
     const uint32_t Bp = (ix.p.B + 3) & ~3u;
-    return q_shape(ix.p.L, ix.p.R, Bp, k).lds;
+    return q_shape(ix.p.L, ix.p.R, Bp, k, sparse_index(ix)).lds;
 }
 
 static int max_lds() {
@@ -1253,7 +1265,7 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.Bp = (ix.p.B + 3) & ~3u;
     a.nbits = ix.nbits;
     a.k = k;
-    const QShape sh = q_shape(a.L, a.R, a.Bp, k);
+    const QShape sh = q_shape(a.L, a.R, a.Bp, k, sparse_index(ix));
     a.threads = (uint32_t)sh.T;
     a.cap = sh.cap;
     a.hc = sh.hc;

@@ -39,7 +39,11 @@ namespace flinng {
 // values do not serialise on one LDS address; HC is a power of two sized to
 // the LDS left over.
 constexpr uint32_t HC_MAX = 32;
-constexpr uint32_t BUDGET = 8192;  // target candidates for the first pass
+// Target members for the first pass.  The pass schedule does not change the
+// answer, only how many members are read: dense indexes (many short-range
+// candidates) do best with a tight first pass, sparse ones (few candidates,
+// near-duplicate clusters) with one large enough to be final more often.
+constexpr uint32_t BUDGET_DENSE = 8192, BUDGET_SPARSE = 32768;
 // positive-cell list capacity (at least one round of T cells)
 __host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 256u : 1024u; }
 // capacity of the list of cells a sparse query touched (fast path)
@@ -1271,7 +1275,7 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.hc = sh.hc;
     a.mstride = ix.mstride;
     a.inv_bp = 1.0f / (float)a.Bp;
-    a.budget = BUDGET;
+    a.budget = sparse_index(ix) ? BUDGET_SPARSE : BUDGET_DENSE;
     return a;
 }
 

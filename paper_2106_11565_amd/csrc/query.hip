@@ -40,10 +40,12 @@ namespace flinng {
 // the LDS left over.
 constexpr uint32_t HC_MAX = 32;
 // Target members for the first pass.  The pass schedule does not change the
-// answer, only how many members are read: dense indexes (many short-range
-// candidates) do best with a tight first pass, sparse ones (few candidates,
+// answer, only how many members are read: dense indexes (many candidates at
+// every level) do best with a tight first pass, sparse ones (few candidates,
 // near-duplicate clusters) with one large enough to be final more often.
-constexpr uint32_t BUDGET_DENSE = 8192, BUDGET_SPARSE = 32768;
+// (Measured on the 1M x 4096 ReLU index for dense, 2048-16384 tried, and on
+// the 5M URL and configured genome indexes for sparse, 8192-65536 tried.)
+constexpr uint32_t BUDGET_DENSE = 4096, BUDGET_SPARSE = 32768;
 // positive-cell list capacity (at least one round of T cells)
 __host__ __device__ constexpr uint32_t cl_for(int T) { return T <= 256 ? 256u : 1024u; }
 // capacity of the list of cells a sparse query touched (fast path)

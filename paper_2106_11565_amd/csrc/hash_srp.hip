@@ -111,6 +111,23 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
     if (row == 0 && lane < 2) ctr[lane] = 0ull;
     const uint64_t plane_stride = n * dpad;
     float s = 0.f;
+    if (!F32 && planes == nullptr && d == dpad) {
+        // bf16 rows used in place (16-byte aligned, d a multiple of 32):
+        // only the norm, from 16-byte loads (eight values per lane)
+        const uint4 *xr = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(xin) + row * d);
+        for (uint32_t i = lane; i < d / 8; i += 64) {
+            const uint4 v = xr[i];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float lo = __uint_as_float(w[j] << 16), hi = __uint_as_float(w[j] & 0xFFFF0000u);
+                s += lo * lo + hi * hi;
+            }
+        }
+        s = wave_sum_f32(s);
+        if (lane == 0) nx[row] = sqrtf(s);
+        return;
+    }
     for (uint32_t i = lane; i < dpad; i += 64) {
         float x = 0.f;
         if (i < d) {

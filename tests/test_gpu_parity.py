@@ -262,3 +262,34 @@ def test_query_streams_and_threads(fl):
     got_i, got_s = gi.query((dev(big_it), dev(big_of)), 10, stream=streams[0])
     assert np.array_equal(got_i[:nq], want_i) and np.array_equal(got_i[nq:], want_i)
     assert np.array_equal(got_s[:nq], want_s) and np.array_equal(got_s[nq:], want_s)
+
+
+def test_sparse_counting_touched_list_overflow(fl):
+    """Sparse queries (list entries at most the counter words) note the cells
+    they touch in a 256-entry list; a query touching more cells builds its
+    positive-cell lists by scanning instead.  Short MinHash buckets over a
+    small grid give sparse queries on both sides of that limit and a few
+    dense ones in one batch; the answers equal the oracle's in both launch
+    modes."""
+    rng = np.random.default_rng(5)
+    pool = rng.integers(0, 2**32, 20000, dtype=np.uint64).astype(np.uint32)
+    it, of = random_sets(rng, 4096, 20, np.uint32, pool=pool)
+    qit, qof = random_sets(rng, 96, 20, np.uint32, pool=pool)
+    K, L, R, B, bits = 1, 4, 4, 1024, 8
+    gi, oi = build_both(fl, 2, (it, of), K, L, R, B, 31, bits)
+    codes = oi.hash((qit, qof))
+    cnt = oi.counts(codes)
+    nent = np.array([sum(int(oi.offsets[t, c + 1] - oi.offsets[t, c]) for t, c in enumerate(row))
+                     for row in codes])
+    words = ((R * ((B + 3) & ~3)) // 4 + 3) & ~3
+    touched = (cnt > 0).sum(axis=1)
+    sparse = nent <= words
+    log("entries", nent.min(), nent.max(), "touched", touched.min(), touched.max(), "words", words)
+    # sparse queries on both sides of the list's capacity, and dense ones
+    assert np.any(sparse & (touched > 256)) and np.any(sparse & (touched <= 256))
+    assert np.any(~sparse)
+    for k in (1, 10, 64, 65):
+        want_i, want_s = oracle_query(oi, (qit, qof), k)
+        for pers in (False, True):
+            got_i, got_s = gi.query((qit, qof), k, persistent=pers)
+            assert np.array_equal(got_i, want_i) and np.array_equal(got_s, want_s), (k, pers)

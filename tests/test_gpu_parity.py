@@ -293,3 +293,16 @@ def test_sparse_counting_touched_list_overflow(fl):
         for pers in (False, True):
             got_i, got_s = gi.query((qit, qof), k, persistent=pers)
             assert np.array_equal(got_i, want_i) and np.array_equal(got_s, want_s), (k, pers)
+
+
+@pytest.mark.parametrize("B", [4600, 5200])
+def test_one_query_kernel_register_budgets(fl, B):
+    """Per-query states of about 21 and 24 KiB: the launcher picks the
+    one-query kernel built for seven (B = 4600) and six (B = 5200)
+    wavefronts per SIMD, the most the LDS allows; both equal the oracle."""
+    X, Q, _ = synth.dense_gmm(N=12000, d=16, n_centres=40, nq=48)
+    gi, oi = build_both(fl, 0, X, 2, 4, 4, B, 41, 0)
+    for k in (1, 10, 64):
+        want = oracle_query(oi, Q, k)
+        got = gi.query(Q, k)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), k

@@ -14,9 +14,11 @@ CONFIGS = {
     "c1": dict(name="dense_gmm_10k_d128", family=SRP_F32, N=10_000, d=128,
                n_centres=100, K=8, L=4, R=3, B=100, bucket_bits=8, k=10,
                nq=100),
-    # tuned: the fastest (K, L) of a sweep at this R, B whose R1@10 on 3000
-    # queries clears 0.9 by more than two standard errors (K=1, L=8 reaches
-    # 0.904, within one; the configured K=2, L=32 reaches 0.79)
+    # tuned: a (K, L) of a sweep at this R, B whose R1@10 on 3000 queries
+    # clears 0.9 by well over two standard errors: K=1, L=12 reaches 0.936
+    # (8 s.e.).  L=10 (0.919) and L=9 (0.913) also clear it and run 8-13%
+    # faster, but with the decode kernel under half the HBM peak; L=8 (0.904)
+    # is within one s.e.; the configured K=2, L=32 reaches 0.79
     "c2": dict(name="genome_reads_1M_minhash", family=MINHASH_U64,
                n_base=500_000, N=1_000_000, K=2, L=32, R=4, B=4096,
                bucket_bits=20, k=10, nq=10_000, tuned=dict(K=1, L=12)),

@@ -112,6 +112,15 @@ enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_THRL
 // c / d for c < 2^24 and d >= 1, from the float quotient (within one of the
 // true quotient: c is exact in float and the two roundings of c * (1/d)
 // perturb it by less than one for d >= 2; d = 1 is exact) and one correction.
+// A copy of a lane-dependent value that the compiler cannot merge with the
+// original: an LDS address derived from it is then recomputed where it is
+// used instead of being kept live (and spilled) across the whole query.
+__device__ inline uint32_t fresh_copy(uint32_t x) {
+    uint32_t y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
 __device__ inline uint32_t div_small(uint32_t c, uint32_t d, float inv) {
     uint32_t q = (uint32_t)((float)c * inv);
     const int32_t rr = (int32_t)(c - q * d);
@@ -903,7 +912,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 const bool fin = misc[M_NGE] >= k || keep;
                 if (fin && wave == 0) {
                     const uint64_t v = wave_sort64((uint32_t)lane < QW * k ? wlist[lane] : ~0ull, lane);
-                    if ((uint32_t)lane < k) buf[lane] = v;
+                    if ((uint32_t)lane < k) buf[fresh_copy((uint32_t)lane)] = v;
                 }
                 if (fin && wave != 0) break;
             } else if ((uint32_t)tid < QW * k) {
@@ -1064,7 +1073,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 if (tid == 0) misc[M_NEXT] = 0;
                 __syncthreads();
                 {
-                    const uint32_t t = 1 + tid;
+                    const uint32_t t = 1 + fresh_copy((uint32_t)tid);
                     const unsigned long long ml = __ballot(t <= L && (uint64_t)ms[t] * gmax <= lim);
                     if (lane == 0 && (uint32_t)wave * 64 < L) atomicAdd(&misc[M_NEXT], (uint32_t)__popcll(ml));
                 }

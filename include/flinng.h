@@ -81,7 +81,9 @@ typedef struct flinng_input {
     const uint64_t *offsets;  /* sets: count+1 nondecreasing offsets into
                                  values (offsets[0] = 0); dense: NULL         */
     uint64_t count;           /* number of rows / sets                        */
-    uint32_t on_device;       /* 1: values/offsets are device pointers        */
+    uint32_t on_device;       /* 0: host pointers; 1: values and offsets are
+                                 device pointers; 2 (serving only): values on
+                                 the device, offsets on the host              */
     uint32_t reserved;        /* must be 0                                    */
 } flinng_input;
 
@@ -141,7 +143,8 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
 /*
  * flinng_query_codes -- the count + threshold + decode stage alone, for
  * bucket codes already on the device (as flinng_debug_hash produces them).
- *  codes   (device) nq*L uint32, row-major, each < 2^bucket_bits.
+ *  codes   (device) nq*L uint32, row-major, each < 2^bucket_bits; a code
+ *          outside that range matches no bucket, so its table adds nothing.
  *  ids, scores  (device) nq*k uint32 as in flinng_query (scores may be NULL).
  *  stats   (device, optional) 5 uint64 that the launch adds to: reverse-index
  *          list entries read, cell member ids read over all decode passes,
@@ -166,6 +169,23 @@ const char *flinng_last_error(void);
 /* Bucket codes of a batch: codes[count*L] (host or device), row-major. */
 int flinng_debug_hash(const flinng_index *idx, const flinng_input *q,
                       uint32_t *codes, uint32_t out_on_device, void *stream);
+
+/*
+ * The matrix-core projections of a dense batch, before any recheck (the
+ * hashing layer of Section 3: bit j of table t is the sign of x . w_{t*K+j}).
+ *  proj   (host or device per out_on_device, may be NULL) count*L*K float,
+ *         row-major: the fp32 value the BF16 MFMA stage computed for
+ *         x . w_h, h = t*K + j.  Its sign is trusted (no FP64 recheck) only
+ *         when |proj| > gamma * |x|_2 * |w_h|_2 + tau_abs.
+ *  bound  (host, may be NULL) 2 doubles: gamma and tau_abs of that rule.
+ *         gamma = m u / (1 - m u) * (1 + 2^-6), u = 2^-23, with m the
+ *         roundings a product passes through (bf16 rows: min(128, dpad) +
+ *         ceil(dpad / 128); fp32 rows: 3 * dpad; dpad = dim rounded up to
+ *         32); tau_abs = (1 or 3) * dpad * 2^-100.
+ * FLINNG_EINVAL for MinHash indexes.
+ */
+int flinng_debug_projections(const flinng_index *idx, const flinng_input *q, float *proj,
+                             double *bound, uint32_t out_on_device, void *stream);
 
 /* Per-cell collision counts of a batch: counts[count*R*B] uint8 (host or
  * device), cell id c = r*B + b. */
@@ -215,15 +235,36 @@ typedef struct flinng_serve_stats {
 int flinng_serve_create(flinng_index *const *indexes, uint32_t n_idx,
                         const flinng_serve_config *cfg, flinng_server **out);
 
-/* Submit one request (a batch of queries for index slot idx_slot, host
- * input, copied before return).  *ticket identifies it.  FLINNG_EBUSY when
- * the queue is full or the request alone exceeds the memory budget. */
+/* Submit one request (a batch of queries for index slot idx_slot); *ticket
+ * identifies it.  Host input (q->on_device = 0) is copied before return.
+ * Device input (q->on_device = 1) is borrowed: it must hold its final
+ * values at the call (the caller has synchronized the work producing it)
+ * and stay valid until the request completes (poll returns 1 or wait
+ * returns); the batch stages it from device memory.  For device sets the
+ * call reads the count+1 offsets back once (a small synchronous copy);
+ * q->on_device = 2 (device items, host offsets) avoids that read.
+ * FLINNG_EBUSY when the queue is full or the request alone exceeds the
+ * memory budget; FLINNG_EINVAL for bad arguments (k outside 1..4096, empty
+ * request, decreasing offsets, bad slot). */
 int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot,
                         const flinng_input *q, uint32_t k, uint64_t *ticket);
 
-/* Wait for a request; copies its results (count*k each, host) and releases
- * the ticket.  timeout_ns < 0 waits forever.  FLINNG_ETIMEDOUT leaves the
- * ticket valid. */
+/* As flinng_serve_submit, but the batch writes the request's results into
+ * device buffers: ids (device, count*k uint32, required) and scores (device,
+ * count*k uint32, may be NULL), borrowed until the request completes; they
+ * hold the results once poll returns 1 or wait returns.  A serving loop
+ * whose queries and answers stay in HBM (e.g. embeddings produced on the
+ * GPU) moves nothing over PCIe. */
+int flinng_serve_submit_to(flinng_server *srv, uint32_t idx_slot,
+                           const flinng_input *q, uint32_t k, uint32_t *ids,
+                           uint32_t *scores, uint64_t *ticket);
+
+/* Wait for a request and release the ticket.  Requests submitted with
+ * flinng_serve_submit: copies the results (count*k each) into the host
+ * buffers ids (required) and scores (may be NULL).  Requests submitted with
+ * flinng_serve_submit_to: ids and scores are ignored (may be NULL).
+ * timeout_ns < 0 waits forever.  FLINNG_ETIMEDOUT leaves the ticket valid;
+ * FLINNG_ESTATE for an unknown ticket. */
 int flinng_serve_wait(flinng_server *srv, uint64_t ticket, uint32_t *ids,
                       uint32_t *scores, int64_t timeout_ns);
 

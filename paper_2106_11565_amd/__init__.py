@@ -77,6 +77,18 @@ class Index:
                                       _stream(stream)))
         return codes
 
+    def debug_projections(self, q, stream=None):
+        """(proj [n, L*K] float32 before any recheck, (gamma, tau_abs)):
+        the matrix-core projections and the bound under which their signs
+        are not trusted (dense indexes)."""
+        inp, keep = make_input(q, self.family)
+        i = self.info
+        proj = np.empty((inp.count, i.L * i.K), dtype=np.float32)
+        bound = (ctypes.c_double * 2)()
+        check(lib().flinng_debug_projections(self._h, ctypes.byref(inp), proj.ctypes.data,
+                                             bound, 0, _stream(stream)))
+        return proj, (bound[0], bound[1])
+
     def debug_counts(self, q, stream=None):
         inp, keep = make_input(q, self.family)
         c = np.empty((inp.count, self.info.R * self.info.B), dtype=np.uint8)
@@ -132,6 +144,22 @@ class Server:
         t = ctypes.c_uint64()
         check(lib().flinng_serve_submit(self._h, slot, ctypes.byref(inp), k, ctypes.byref(t)))
         return t.value, int(inp.count)
+
+    def submit_to(self, slot, q, k, out):
+        """Device request: q on the device (torch tensors, borrowed until
+        the request completes) and out = (ids, scores or None) device
+        tensors the batch writes into.  Complete it with wait_done."""
+        inp, keep = make_input(q, self._family(slot))
+        ids_t, sc_t = out
+        t = ctypes.c_uint64()
+        check(lib().flinng_serve_submit_to(self._h, slot, ctypes.byref(inp), k, ids_t.data_ptr(),
+                                           sc_t.data_ptr() if sc_t is not None else None,
+                                           ctypes.byref(t)))
+        return t.value, int(inp.count)
+
+    def wait_done(self, ticket, timeout_ns=-1):
+        """Wait for a request submitted with submit_to."""
+        check(lib().flinng_serve_wait(self._h, ticket, None, None, timeout_ns))
 
     def try_submit(self, slot, q, k):
         """Like submit, but returns (None, rc) instead of raising on refusal."""

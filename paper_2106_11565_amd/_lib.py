@@ -78,9 +78,12 @@ def lib():
             "flinng_last_error": (ctypes.c_char_p, []),
             "flinng_debug_hash": (ctypes.c_int, [c_vp, P(Input), c_vp, c_u32, c_vp]),
             "flinng_debug_counts": (ctypes.c_int, [c_vp, P(Input), c_vp, c_u32, c_vp]),
+            "flinng_debug_projections": (ctypes.c_int, [c_vp, P(Input), c_vp, c_vp, c_u32, c_vp]),
             "flinng_index_export": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
             "flinng_serve_create": (ctypes.c_int, [P(c_vp), c_u32, P(ServeConfig), P(c_vp)]),
             "flinng_serve_submit": (ctypes.c_int, [c_vp, c_u32, P(Input), c_u32, P(c_u64)]),
+            "flinng_serve_submit_to": (ctypes.c_int, [c_vp, c_u32, P(Input), c_u32, c_vp, c_vp,
+                                                      P(c_u64)]),
             "flinng_serve_wait": (ctypes.c_int, [c_vp, c_u64, c_vp, c_vp, c_i64]),
             "flinng_serve_poll": (ctypes.c_int, [c_vp, c_u64]),
             "flinng_serve_stats_get": (ctypes.c_int, [c_vp, P(ServeStats)]),
@@ -126,7 +129,14 @@ def make_input(data, family):
     else:
         items, offs = data
         want = np.uint64 if family == MINHASH_U64 else np.uint32
-        if _is_torch(items):
+        if _is_torch(items) and not _is_torch(offs):
+            # device items with host offsets (accepted by the server only)
+            assert items.is_cuda
+            of = np.ascontiguousarray(offs, dtype=np.uint64)
+            inp.values, inp.offsets = items.data_ptr(), of.ctypes.data
+            inp.count, inp.on_device = of.shape[0] - 1, 2
+            keep += [items, of]
+        elif _is_torch(items):
             assert items.is_cuda and offs.is_cuda
             inp.values, inp.offsets = items.data_ptr(), offs.data_ptr()
             inp.count, inp.on_device = offs.shape[0] - 1, 1

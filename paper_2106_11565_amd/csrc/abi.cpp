@@ -84,6 +84,7 @@ static void validate_params(const flinng_params &p, uint64_t N) {
 static void validate_input(const flinng_input *in, uint32_t family, const char *what) {
     require(in != nullptr, std::string(what) + " is NULL");
     require(in->reserved == 0, std::string(what) + ".reserved must be 0");
+    require(in->on_device <= 1, std::string(what) + ".on_device must be 0 or 1");
     if (in->count == 0) return;
     require(in->values != nullptr || !is_dense(family), std::string(what) + ".values is NULL");
     if (!is_dense(family)) require(in->offsets != nullptr, std::string(what) + ".offsets is NULL");
@@ -317,6 +318,32 @@ int flinng_debug_hash(const flinng_index *idx, const flinng_input *q, uint32_t *
             DevBuf d(nq * ix.p.L * 4, s);
             hash_batch(ix, *q, d.as<uint32_t>(), s, nullptr);
             FL_HIP(hipMemcpyAsync(codes, d.ptr, nq * ix.p.L * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+int flinng_debug_projections(const flinng_index *idx, const flinng_input *q, float *proj,
+                             double *bound, uint32_t out_on_device, void *stream) {
+    return guard([&] {
+        require(idx != nullptr, "index is NULL");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        require(is_dense(ix.p.family), "projections exist for dense (SRP) indexes only");
+        if (bound) srp_bound(ix, &bound[0], &bound[1]);
+        if (!proj) return;
+        validate_input(q, ix.p.family, "queries");
+        const uint64_t nq = q->count;
+        if (nq == 0) return;
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const uint64_t H = (uint64_t)ix.p.L * ix.p.K;
+        DevBuf codes(nq * ix.p.L * 4, s);
+        if (out_on_device) {
+            srp_hash(ix, *q, codes.as<uint32_t>(), s, nullptr, nullptr, proj);
+        } else {
+            DevBuf d(nq * H * 4, s);
+            srp_hash(ix, *q, codes.as<uint32_t>(), s, nullptr, nullptr, d.as<float>());
+            FL_HIP(hipMemcpyAsync(proj, d.ptr, nq * H * 4, hipMemcpyDeviceToHost, s));
             FL_HIP(hipStreamSynchronize(s));
         }
     });

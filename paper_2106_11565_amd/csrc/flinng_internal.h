@@ -164,8 +164,14 @@ struct Scratch {
 void srp_make_hyperplanes(Index &ix, hipStream_t s);
 // Returns (rechecked, exact) counts when counters != nullptr (synchronizes).
 // Scratch comes from ws when given (srp_scratch_bytes bounds what it takes).
+// proj_dev (optional, device, n*L*K fp32): receives the MFMA projections
+// before any recheck.
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
-              hipStream_t s, uint64_t *counters_host, Arena *ws = nullptr);
+              hipStream_t s, uint64_t *counters_host, Arena *ws = nullptr,
+              float *proj_dev = nullptr);
+// The error bound the MFMA stage uses for a trusted sign: |v32 - v| <=
+// gamma * |x|_2 * |w|_2 + tau_abs (rounding of the norms included).
+void srp_bound(const Index &ix, double *gamma, double *tau_abs);
 // Upper bound of the scratch srp_hash takes for n rows already on the device.
 size_t srp_scratch_bytes(const Index &ix, uint64_t n);
 void minhash_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,

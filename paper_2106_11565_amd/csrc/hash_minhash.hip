@@ -85,8 +85,14 @@ template <typename ItemT>
 static void launch_minhash(int S, const ItemT *items, const uint64_t *offs, uint64_t n,
                            uint32_t K, uint32_t L, uint32_t b, uint64_t key, uint32_t *codes,
                            hipStream_t s) {
-    dim3 grid((unsigned)((n + 3) / 4)), block(256);
-    size_t lds = 4 * (size_t)L * K * sizeof(uint32_t);
+    // one wavefront per set, up to four per workgroup: as many as keep the
+    // per-wavefront minima (L*K words each) within 64 KiB of LDS, so every
+    // valid (K, L) launches (L*K <= 255*32 needs 32 KiB for one wavefront)
+    const size_t per_wave = (size_t)L * K * sizeof(uint32_t);
+    unsigned waves = 4;
+    while (waves > 1 && waves * per_wave > 65536) waves >>= 1;
+    dim3 grid((unsigned)((n + waves - 1) / waves)), block(64 * waves);
+    size_t lds = waves * per_wave;
     hipLaunchKernelGGL((minhash_kernel<ItemT>), grid, block, lds, s, items, offs, n, K, L, b, key,
                        (uint32_t)S, codes);
     FL_CHECK_LAUNCH();

@@ -90,9 +90,13 @@ void srp_make_hyperplanes(Index &ix, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Prep: one wavefront per row.  Writes nsplit bf16 planes [n][dpad] (unless
-// planes == nullptr) and the fp32 row norm.  fp32 values are split by
-// truncation: x = x1 + x2 + x3, each a bf16 (exact except below 2^-133,
-// which the denormal allowance of tau covers).
+// planes == nullptr) and the row norm, rounded to fp32.  fp32 values are
+// split by truncation: x = x1 + x2 + x3, each a bf16 (exact except below
+// 2^-133, which the denormal allowance of tau covers).
+// The sum of squares is accumulated in FP64: the square of any fp32 or bf16
+// value (at least 2^-298) is a normal double, so the norm cannot underflow
+// for rows whose entries all lie below 2^-63, where fp32 squares would
+// vanish and leave the sign certificate with the absolute term alone.
 template <bool F32>
 __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d,
                             uint32_t dpad, uint16_t *__restrict__ planes,
@@ -110,7 +114,7 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
     }
     if (row == 0 && lane < 2) ctr[lane] = 0ull;
     const uint64_t plane_stride = n * dpad;
-    float s = 0.f;
+    double s = 0.0;
     if (!F32 && planes == nullptr && d == dpad) {
         // bf16 rows used in place (16-byte aligned, d a multiple of 32):
         // only the norm, from 16-byte loads (eight values per lane)
@@ -120,12 +124,13 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float lo = __uint_as_float(w[j] << 16), hi = __uint_as_float(w[j] & 0xFFFF0000u);
+                const double lo = (double)__uint_as_float(w[j] << 16);
+                const double hi = (double)__uint_as_float(w[j] & 0xFFFF0000u);
                 s += lo * lo + hi * hi;
             }
         }
-        s = wave_sum_f32(s);
-        if (lane == 0) nx[row] = sqrtf(s);
+        s = wave_sum_f64(s);
+        if (lane == 0) nx[row] = (float)sqrt(s);
         return;
     }
     for (uint32_t i = lane; i < dpad; i += 64) {
@@ -136,7 +141,7 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
             else
                 x = bf16_to_f32(static_cast<const uint16_t *>(xin)[row * d + i]);
         }
-        s += x * x;
+        s += (double)x * (double)x;
         if (planes) {
             uint64_t o = row * dpad + i;
             if (F32) {
@@ -155,8 +160,8 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
             (void)plane_stride;
         }
     }
-    s = wave_sum_f32(s);
-    if (lane == 0) nx[row] = sqrtf(s);
+    s = wave_sum_f64(s);
+    if (lane == 0) nx[row] = (float)sqrt(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,7 +178,8 @@ __global__ __launch_bounds__(64 * WM * WN) void srp_mfma_kernel(
     const uint16_t *__restrict__ w, uint32_t dpad, const float *__restrict__ nx,
     const float *__restrict__ nw, uint64_t n, uint32_t H, uint32_t Hw,
     float gamma, float tau_abs, uint16_t *__restrict__ bits16,
-    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag) {
+    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag,
+    float *__restrict__ proj) {
     const int lane = threadIdx.x % 64;
     const int wave = threadIdx.x / 64;
     const int wm = wave / WN, wn = wave % WN;
@@ -239,6 +245,7 @@ __global__ __launch_bounds__(64 * WM * WN) void srp_mfma_kernel(
                 const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
                 const float xn = (row < n) ? nx[row] : 0.f;
                 const float v = acc[a][b][i];
+                if (proj && row < n && col < H) proj[row * H + col] = v;
                 const float tau = gamma * xn * wn_ + tau_abs;
                 const bool ok = (col < H) && (fabsf(v) > tau);
                 const bool bit = ok && (v > 0.f);
@@ -286,7 +293,8 @@ __global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
     const uint16_t *__restrict__ planes, uint32_t ld, const uint16_t *__restrict__ w,
     uint32_t dpad, const float *__restrict__ nx, const float *__restrict__ nw, uint64_t n,
     uint32_t H, uint32_t Hw, float gamma, float tau_abs, uint16_t *__restrict__ bits16,
-    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag) {
+    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag,
+    float *__restrict__ proj) {
     __shared__ __align__(16) uint16_t sa[2][LT * LROW];
     __shared__ __align__(16) uint16_t sb[2][LT * LROW];
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -392,6 +400,7 @@ __global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
                 const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
                 const float xn = (row < n) ? nx[row] : 0.f;
                 const float v = acc[a][b][i];
+                if (proj && row < n && col < H) proj[row * H + col] = v;
                 const float tau = gamma * xn * wn_ + tau_abs;
                 const bool ok = (col < H) && (fabsf(v) > tau);
                 const bool bit = ok && (v > 0.f);
@@ -647,6 +656,20 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Roundings a product can pass through: one long chain of 3 * dpad terms for
+// the fp32 kernel (three bf16 planes); chunked for the LDS kernel (bf16).
+// gamma_m = m u / (1 - m u) with u = 2^-23, widened by 2^-6 for the fp32
+// rounding of the two norms and of gamma itself; the absolute term covers
+// products and partial sums that the matrix cores flush below 2^-126.
+void srp_bound(const Index &ix, double *gamma, double *tau_abs) {
+    const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
+    const double nterms =
+        nsplit == 1 ? (double)srp_lds_terms(ix.dpad) : (double)nsplit * ix.dpad;
+    const double u = 0x1p-23;
+    *gamma = nterms * u / (1.0 - nterms * u) * (1.0 + 0x1p-6);
+    *tau_abs = (double)nsplit * ix.dpad * 0x1p-100;
+}
+
 size_t srp_scratch_bytes(const Index &ix, uint64_t n) {
     const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
     const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
@@ -655,7 +678,7 @@ size_t srp_scratch_bytes(const Index &ix, uint64_t n) {
 }
 
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
-              uint64_t *counters_host, Arena *ws) {
+              uint64_t *counters_host, Arena *ws, float *proj_dev) {
     const uint64_t n = in.count;
     if (n == 0) return;
     const uint32_t d = ix.p.dim, dpad = ix.dpad;
@@ -694,13 +717,10 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     const uint32_t ld = inplace ? d : dpad;
     const uint64_t pstride = (uint64_t)n * dpad;
 
-    // roundings a product can pass through: one long chain of nsplit * dpad
-    // terms for the direct kernel; chunked for the LDS kernel (bf16)
-    const double nterms = nsplit == 1 ? (double)srp_lds_terms(dpad) : (double)nsplit * dpad;
-    const double u = 0x1p-23;
-    const double gam = nterms * u / (1.0 - nterms * u) * (1.0 + 0x1p-6);
+    double gam = 0.0, tabs = 0.0;
+    srp_bound(ix, &gam, &tabs);
     const float gamma = (float)gam;
-    const float tau_abs = (float)((double)nsplit * dpad * 0x1p-100);
+    const float tau_abs = (float)tabs;
 
     constexpr int MR = 4, NR = 4, WM = 2, WN = 2;
     dim3 grid((H + 16 * NR * WN - 1) / (16 * NR * WN),
@@ -710,13 +730,13 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 3>), grid, dim3(64 * WM * WN), 0, s,
                            pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
                            reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
-                           nflag);
+                           nflag, proj_dev);
     else
         hipLaunchKernelGGL(srp_mfma_lds_kernel,
                            dim3((H + LT - 1) / LT, (unsigned)((n + LT - 1) / LT)), dim3(256), 0, s,
                            pl, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
                            reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
-                           nflag);
+                           nflag, proj_dev);
     FL_CHECK_LAUNCH();
     if (inplace)
         hipLaunchKernelGGL(srp_recheck_pack_vec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),

@@ -543,10 +543,14 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         constexpr uint32_t CE = 16 / sizeof(CellT);  // list entries per chunk
         uint32_t nch = 0, st = 0, en = 0;
         if ((uint32_t)tid < L) {
+            // a code outside the table (caller-supplied codes) matches no
+            // bucket: its table adds nothing
             const uint32_t h = A.codes[q * L + tid];
-            const uint32_t *o = A.offsets + (uint64_t)tid * nbk1 + h;
-            st = o[0];
-            en = o[1];
+            if ((uint64_t)h + 1 < nbk1) {
+                const uint32_t *o = A.offsets + (uint64_t)tid * nbk1 + h;
+                st = o[0];
+                en = o[1];
+            }
         }
         {
             uint4 *c16 = reinterpret_cast<uint4 *>(cnt32);
@@ -1166,44 +1170,43 @@ size_t query_lds_bytes(const Index &ix, uint32_t k) {
     return q_shape(ix.p.L, ix.p.R, Bp, k, sparse_index(ix)).lds;
 }
 
-static int max_lds() {
-    static int v = 0;
-    if (!v) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        int x = 0;
-        if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || x <= 0)
-            x = 65536;
-        v = x;
+// Device attributes read once per process (function-local statics are
+// initialised exactly once even when several threads launch at the same time;
+// every device this library runs on is an MI355X, so one reading serves all).
+static int device_attr(hipDeviceAttribute_t attr, int fallback) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int x = 0;
+    if (hipDeviceGetAttribute(&x, attr, dev) != hipSuccess || x <= 0) {
+        (void)hipGetLastError();
+        x = fallback;
     }
+    return x;
+}
+
+static int max_lds() {
+    static const int v = device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536);
     return v;
 }
 
 static int num_cus() {
-    static int v = 0;
-    if (!v) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        int x = 0;
-        if (hipDeviceGetAttribute(&x, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || x <= 0)
-            x = 256;
-        v = x;
-    }
+    static const int v = device_attr(hipDeviceAttributeMultiprocessorCount, 256);
     return v;
 }
 
 template <typename CellT, int RP, int QT, bool GK, bool PERS, int WAVES>
 static void launch_kernel(const QArgs &a, size_t lds, unsigned grid, hipStream_t s) {
-    static bool attr_set = false;
-    if (!attr_set) {
+    // once per kernel variant and process (a throwing initialiser is retried)
+    static const bool attrs_ok = [] {
         const void *fn = reinterpret_cast<const void *>(&query_kernel<CellT, RP, QT, GK, PERS, WAVES>);
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds());
         // the counters are addressed from LDS address 0 (dynamic LDS first)
         hipFuncAttributes fa{};
         if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes != 0)
             fail(FLINNG_EDEVICE, "query kernel: static LDS in use or attributes unavailable");
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attrs_ok;
     hipLaunchKernelGGL((query_kernel<CellT, RP, QT, GK, PERS, WAVES>), dim3(grid), dim3(QT), lds, s, a);
 }
 

@@ -1,7 +1,10 @@
 // Continuous-batching query server over resident FLINNG indexes.
 //
 // Requests (a batch of queries for one index slot) are copied at submit and
-// queued.  One scheduler thread keeps up to max_inflight batches on the GPU,
+// queued; device-resident requests are borrowed instead (their values are
+// staged from device memory by the batch, and their results can be written
+// straight into device buffers).  One scheduler thread keeps up to
+// max_inflight batches on the GPU,
 // one per HIP stream (all at the default priority): whenever a stream is free
 // and the memory budget admits it, it coalesces queued requests of the same
 // (index, k) into one batch and enqueues a copy kernel that pulls every
@@ -17,6 +20,7 @@
 // recorded.  Every query is decoded by its own workgroup from its own codes,
 // so a request's results do not depend on what it was batched with.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -148,6 +152,9 @@ struct Request {
     size_t vbytes = 0;
     std::vector<unsigned char> values;  // small payloads (or the pool is full)
     Pinned pinned;                       // large payloads: a block of the pool
+    uint64_t dev_values = 0;             // device-resident payload (borrowed)
+    uint32_t *out_ids = nullptr;         // device outputs (borrowed), or null:
+    uint32_t *out_scores = nullptr;      // results are kept for wait()
     int pcls = -1;
     PinnedPool *pool = nullptr;
     std::vector<uint64_t> offsets;  // rebased to 0 (sets)
@@ -290,7 +297,10 @@ static void launch(Server &S, Lane &ln) {
         run_len = 0;
     };
     for (Request *r : ln.reqs) {
-        if (r->pinned.host) {
+        if (r->dev_values) {
+            flush();
+            if (r->vbytes) ln.segs.push_back({r->dev_values, dev_in + dst, r->vbytes});
+        } else if (r->pinned.host) {
             flush();
             ln.segs.push_back({r->pinned.dev, dev_in + dst, r->vbytes});
         } else if (r->vbytes) {
@@ -330,9 +340,29 @@ static void launch(Server &S, Lane &ln) {
     hash_batch(ix, in, codes, s, nullptr, dense ? -1.0 : (double)ln.nitems / (double)nq, &ws);
     query_launch(ix, codes, nq, k, out, out + nq * k, S.cfg.persistent != 0, s,
                  reinterpret_cast<uint32_t *>(base + pl.work));
-    ensure_pinned(&ln.hout, &ln.hout_cap, 2 * nq * k * 4);
-    const CopySeg back{reinterpret_cast<uint64_t>(out), ln.hout.dev, 2 * nq * k * 4};
-    copy_segments(&back, 1, s);
+    // results: requests with device outputs get their slices copied there,
+    // the others share one copy of the whole batch into pinned host memory
+    ln.segs.clear();
+    bool to_host = false;
+    uint64_t qi = 0;
+    const uint64_t dout = reinterpret_cast<uint64_t>(out);
+    for (Request *r : ln.reqs) {
+        if (r->out_ids) {
+            ln.segs.push_back({dout + qi * k * 4, reinterpret_cast<uint64_t>(r->out_ids),
+                               r->nq * k * 4});
+            if (r->out_scores)
+                ln.segs.push_back({dout + (nq + qi) * k * 4,
+                                   reinterpret_cast<uint64_t>(r->out_scores), r->nq * k * 4});
+        } else {
+            to_host = true;
+        }
+        qi += r->nq;
+    }
+    if (to_host) {
+        ensure_pinned(&ln.hout, &ln.hout_cap, 2 * nq * k * 4);
+        ln.segs.push_back({dout, ln.hout.dev, 2 * nq * k * 4});
+    }
+    copy_segments(ln.segs.data(), ln.segs.size(), s);
     FL_HIP(hipEventRecord(ln.done, s));
 }
 
@@ -343,7 +373,7 @@ static void finish(Server &S, Lane &ln) {
     const uint32_t *sc = ids + ln.nq * ln.k;
     uint64_t qi = 0;
     for (Request *r : ln.reqs) {
-        if (ln.status == 0) {
+        if (ln.status == 0 && !r->out_ids) {
             r->ids.assign(ids + qi * ln.k, ids + (qi + r->nq) * ln.k);
             r->scores.assign(sc + qi * ln.k, sc + (qi + r->nq) * ln.k);
         }
@@ -361,9 +391,18 @@ static void finish(Server &S, Lane &ln) {
     S.cv_done.notify_all();
 }
 
+// Completion polling period while batches are in flight (a new request
+// wakes the scheduler at once).
+constexpr int POLL_US = 4;
+
 static void scheduler(Server *Sp) {
     Server &S = *Sp;
     (void)hipSetDevice(S.device);
+    // Wake-ups while batches are in flight are timed waits of a few
+    // microseconds; Linux lets a timed wait overshoot by the thread's timer
+    // slack (50 us by default), which would delay every completion by that
+    // much.  Ask for 1 us (unprivileged; ignored where unsupported).
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(S.mu);
     for (;;) {
         // 1. retire completed batches
@@ -471,7 +510,7 @@ static void scheduler(Server *Sp) {
         bool busy = false;
         for (Lane &ln : S.lanes) busy |= ln.busy;
         if (busy)
-            S.cv_sched.wait_for(lk, std::chrono::microseconds(20));
+            S.cv_sched.wait_for(lk, std::chrono::microseconds(POLL_US));
         else if (!S.stop && wake != Clock::time_point::max())
             S.cv_sched.wait_until(lk, wake);
         else if (!S.stop)
@@ -563,67 +602,103 @@ int flinng_serve_create(flinng_index *const *indexes, uint32_t n_idx, const flin
     });
 }
 
-int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_input *q, uint32_t k,
-                        uint64_t *ticket) {
-    return sguard([&] {
-        if (!srv || !q || !ticket) fail(FLINNG_EINVAL, "NULL argument");
-        Server &S = *reinterpret_cast<Server *>(srv);
-        if (idx_slot >= S.idx.size()) fail(FLINNG_EINVAL, "bad index slot");
-        if (k < 1 || k > query_max_k()) fail(FLINNG_EINVAL, "k must be in 1..4096");
-        if (q->count == 0) fail(FLINNG_EINVAL, "empty request");
-        if (q->on_device) fail(FLINNG_EINVAL, "serving takes host inputs");
-        const Index &ix = *S.idx[idx_slot];
-        Request *r = new Request();
-        r->pool = &S.pool;
-        r->slot = idx_slot;
-        r->k = k;
-        r->nq = q->count;
-        if (is_dense(ix.p.family)) {
-            if (!q->values) {
-                delete r;
-                fail(FLINNG_EINVAL, "values is NULL");
-            }
-            const size_t esz = ix.p.family == FLINNG_SRP_F32 ? 4 : 2;
-            const size_t bytes = q->count * ix.p.dim * esz;
-            r->set_payload(static_cast<const unsigned char *>(q->values), bytes);
+}  // extern "C"
+
+namespace flinng {
+
+// Submit one request (both ABI entry points).  Host inputs are copied;
+// device inputs are borrowed until the request completes (set offsets are
+// read back once, here, to size the batch).  out_ids/out_scores: device
+// buffers the batch writes the results into, or null (kept for wait()).
+static void submit_request(Server &S, uint32_t idx_slot, const flinng_input *q, uint32_t k,
+                           uint32_t *out_ids, uint32_t *out_scores, uint64_t *ticket) {
+    if (!q || !ticket) fail(FLINNG_EINVAL, "NULL argument");
+    if (idx_slot >= S.idx.size()) fail(FLINNG_EINVAL, "bad index slot");
+    if (k < 1 || k > query_max_k()) fail(FLINNG_EINVAL, "k must be in 1..4096");
+    if (q->count == 0) fail(FLINNG_EINVAL, "empty request");
+    if (q->reserved != 0) fail(FLINNG_EINVAL, "queries.reserved must be 0");
+    if (q->on_device > 2) fail(FLINNG_EINVAL, "queries.on_device must be 0, 1 or 2");
+    const Index &ix = *S.idx[idx_slot];
+    std::unique_ptr<Request> r(new Request());
+    r->pool = &S.pool;
+    r->slot = idx_slot;
+    r->k = k;
+    r->nq = q->count;
+    r->out_ids = out_ids;
+    r->out_scores = out_ids ? out_scores : nullptr;
+    if (is_dense(ix.p.family)) {
+        if (!q->values) fail(FLINNG_EINVAL, "values is NULL");
+        const size_t esz = ix.p.family == FLINNG_SRP_F32 ? 4 : 2;
+        const size_t bytes = q->count * ix.p.dim * esz;
+        if (q->on_device) {
+            r->vbytes = bytes;
+            r->dev_values = reinterpret_cast<uint64_t>(q->values);
         } else {
-            if (!q->offsets) {
-                delete r;
-                fail(FLINNG_EINVAL, "offsets is NULL");
-            }
-            const uint64_t first = q->offsets[0], last = q->offsets[q->count];
-            const size_t isz = ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4;
-            r->offsets.resize(q->count + 1);
-            for (uint64_t i = 0; i <= q->count; ++i) {
-                if (i && q->offsets[i] < q->offsets[i - 1]) {
-                    delete r;
-                    fail(FLINNG_EINVAL, "offsets must be nondecreasing");
-                }
-                r->offsets[i] = q->offsets[i] - first;
-            }
-            r->nitems = last - first;
+            r->set_payload(static_cast<const unsigned char *>(q->values), bytes);
+        }
+    } else {
+        if (!q->offsets) fail(FLINNG_EINVAL, "offsets is NULL");
+        if (!q->values && q->on_device) fail(FLINNG_EINVAL, "values is NULL");
+        r->offsets.resize(q->count + 1);
+        if (q->on_device == 1) {
+            FL_HIP(hipSetDevice(S.device));
+            FL_HIP(hipMemcpy(r->offsets.data(), q->offsets, (q->count + 1) * 8,
+                             hipMemcpyDeviceToHost));
+        } else {
+            std::memcpy(r->offsets.data(), q->offsets, (q->count + 1) * 8);
+        }
+        const uint64_t first = r->offsets[0], last = r->offsets[q->count];
+        for (uint64_t i = 0; i <= q->count; ++i) {
+            if (i && r->offsets[i] < r->offsets[i - 1])
+                fail(FLINNG_EINVAL, "offsets must be nondecreasing");
+            r->offsets[i] -= first;
+        }
+        const size_t isz = ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4;
+        r->nitems = last - first;
+        if (r->nitems && !q->values) fail(FLINNG_EINVAL, "values is NULL");
+        if (q->on_device) {
+            r->vbytes = r->nitems * isz;
+            r->dev_values = reinterpret_cast<uint64_t>(q->values) + first * isz;
+        } else {
             const unsigned char *v = static_cast<const unsigned char *>(q->values) + first * isz;
             r->set_payload(v, r->nitems * isz);
         }
-        r->mem = batch_device_bytes(ix, r->nq, r->nitems, k);
-        std::lock_guard<std::mutex> lk(S.mu);
-        if (S.stop) {
-            delete r;
-            fail(FLINNG_ESTATE, "server is shutting down");
-        }
-        if (r->mem > S.cfg.mem_budget || S.queue.size() >= S.cfg.max_queue) {
-            S.rejected++;
-            const bool big = r->mem > S.cfg.mem_budget;
-            delete r;
-            fail(FLINNG_EBUSY, big ? "request exceeds the memory budget" : "queue full");
-        }
-        r->ticket = S.next_ticket++;
-        r->t_submit = Clock::now();
-        S.tickets[r->ticket] = r;
-        S.queue.push_back(r);
-        S.submitted++;
-        *ticket = r->ticket;
-        S.cv_sched.notify_one();
+    }
+    r->mem = batch_device_bytes(ix, r->nq, r->nitems, k);
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stop) fail(FLINNG_ESTATE, "server is shutting down");
+    if (r->mem > S.cfg.mem_budget || S.queue.size() >= S.cfg.max_queue) {
+        S.rejected++;
+        fail(FLINNG_EBUSY, r->mem > S.cfg.mem_budget ? "request exceeds the memory budget"
+                                                     : "queue full");
+    }
+    Request *rp = r.release();
+    rp->ticket = S.next_ticket++;
+    rp->t_submit = Clock::now();
+    S.tickets[rp->ticket] = rp;
+    S.queue.push_back(rp);
+    S.submitted++;
+    *ticket = rp->ticket;
+    S.cv_sched.notify_one();
+}
+
+}  // namespace flinng
+
+extern "C" {
+
+int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_input *q, uint32_t k,
+                        uint64_t *ticket) {
+    return sguard([&] {
+        if (!srv) fail(FLINNG_EINVAL, "NULL argument");
+        submit_request(*reinterpret_cast<Server *>(srv), idx_slot, q, k, nullptr, nullptr, ticket);
+    });
+}
+
+int flinng_serve_submit_to(flinng_server *srv, uint32_t idx_slot, const flinng_input *q,
+                           uint32_t k, uint32_t *ids, uint32_t *scores, uint64_t *ticket) {
+    return sguard([&] {
+        if (!srv || !ids) fail(FLINNG_EINVAL, "NULL argument");
+        submit_request(*reinterpret_cast<Server *>(srv), idx_slot, q, k, ids, scores, ticket);
     });
 }
 
@@ -642,7 +717,7 @@ int flinng_serve_poll(flinng_server *srv, uint64_t ticket) {
 int flinng_serve_wait(flinng_server *srv, uint64_t ticket, uint32_t *ids, uint32_t *scores,
                       int64_t timeout_ns) {
     return sguard([&] {
-        if (!srv || !ids) fail(FLINNG_EINVAL, "NULL argument");
+        if (!srv) fail(FLINNG_EINVAL, "NULL argument");
         Server &S = *reinterpret_cast<Server *>(srv);
         std::unique_lock<std::mutex> lk(S.mu);
         auto it = S.tickets.find(ticket);
@@ -654,9 +729,10 @@ int flinng_serve_wait(flinng_server *srv, uint64_t ticket, uint32_t *ids, uint32
         } else if (!S.cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), pred)) {
             fail(FLINNG_ETIMEDOUT, "request not complete");
         }
+        if (!ids && !r->out_ids) fail(FLINNG_EINVAL, "ids is NULL for a request with host results");
         S.tickets.erase(it);
         const int st = r->status;
-        if (st == 0) {
+        if (st == 0 && !r->out_ids) {
             std::memcpy(ids, r->ids.data(), r->ids.size() * 4);
             if (scores) std::memcpy(scores, r->scores.data(), r->scores.size() * 4);
         }

@@ -68,6 +68,89 @@ def test_srp_exact_zero_and_tiny_projections(fl):
     log("rechecked", gi.info.srp_rechecked, "exact", gi.info.srp_exact)
 
 
+def _cancelling_rows(w, rng, nrand, boost=2.0**6, tiny=2.0**-20):
+    """Random rows, then for each hyperplane h a row exactly orthogonal to it
+    whose products with w[h] are all positive on the first half of the
+    coordinates and all negative on the second half (pairs (i, j) of equal
+    hyperplane sign with x_i = w[h, j], x_j = -w[h, i]), so partial sums grow
+    far from the exact total 0; and that row plus / minus `tiny` at a free
+    coordinate (projection exactly +-tiny * w[h, k]).  Values are
+    quarter-integers times powers of two: exact in bf16."""
+    H, d = w.shape
+    rows = [rng.standard_normal(d) for _ in range(nrand)]
+    half = d // 2
+    for h in range(H):
+        wh = w[h]
+        z = np.zeros(d)
+        for sgn in (1, -1):
+            a = [i for i in range(half) if np.sign(wh[i]) == sgn]
+            b = [i for i in range(half, d) if np.sign(wh[i]) == sgn]
+            for i, j in zip(a, b):
+                z[i], z[j] = wh[j], -wh[i]
+        z *= boost
+        rows.append(z.copy())
+        free = [i for i in range(d) if z[i] == 0 and wh[i] != 0]
+        if free:
+            t = z.copy()
+            t[free[0]] = tiny
+            rows.append(t)
+            rows.append(-t)
+    return np.stack(rows)
+
+
+@pytest.mark.parametrize("family,d", [(0, 64), (0, 100), (1, 128), (1, 100)])
+def test_srp_extreme_scales_and_cancellations(fl, family, d):
+    """Rows scaled by 2^0, 2^-70, 2^-80 and 2^-100 (fp32 sums of their
+    squares underflow from 2^-80 on), including exactly cancelling and
+    +-tiny projections: codes equal the oracle's and are the same at every
+    scale (SRP bits are scale invariant).  bf16 rows with d a multiple of 32
+    take the in-place recheck kernel, ragged d the general one; both reach
+    the exact-sum fallback (srp_exact > 0)."""
+    log("srp scales", family, d)
+    K, L, seed = 8, 4, 77
+    w = oracle.hyperplanes(seed, K * L, d)
+    X = _cancelling_rows(w, np.random.default_rng(d + family), 24)
+    n0 = X.shape[0]
+    x = np.concatenate([X * 2.0**-e for e in (0, 70, 80, 100)]).astype(np.float32)
+    xs = synth.f32_to_bf16(x) if family == 1 else x
+    xd = oracle.bf16_to_f64(xs) if family == 1 else x.astype(np.float64)
+    for b in range(1, 4):   # power-of-two scaling stayed exact in storage
+        assert np.array_equal(xd[b * n0:(b + 1) * n0] * 2.0**[0, 70, 80, 100][b], xd[:n0])
+    want = oracle.srp_codes(xd, seed, K, L, w=w)
+    for b in range(1, 4):
+        assert np.array_equal(want[b * n0:(b + 1) * n0], want[:n0])
+    gi = fl.Index(xs, family, K, L, 3, 10, seed=seed)
+    got = gi.debug_hash(xs)
+    bad = np.nonzero(np.any(got != want, axis=1))[0]
+    assert len(bad) == 0, (bad[:8], got[bad[:2]], want[bad[:2]])
+    log("rechecked", gi.info.srp_rechecked, "exact", gi.info.srp_exact)
+    assert gi.info.srp_rechecked > 0 and gi.info.srp_exact > 0
+
+
+def test_mfma_projection_error_within_bound(fl):
+    """The accuracy the sign certificate assumes of the bf16 matrix cores:
+    on ReLU-embedding rows (d = 4096, 1024 hyperplanes) every fp32
+    projection is within half the certified bound of the FP64 value,
+    |v32 - v| < gamma / 2 * |x| |w|, and every trusted sign is right."""
+    cfg, X, Q, _ = scaled("c3", 0.002, 1500)
+    gi = fl.Index(X, 1, cfg["K"], cfg["L"], 2, 16, seed=21)
+    w = oracle.hyperplanes(21, cfg["K"] * cfg["L"], cfg["d"])
+    wn = np.sqrt((w * w).sum(axis=1))
+    worst = 0.0
+    for rows in (Q, X[:1500]):
+        proj, (gamma, tau_abs) = gi.debug_projections(rows)
+        xd = oracle.bf16_to_f64(rows)
+        v = xd @ w.T
+        scale = np.sqrt((xd * xd).sum(axis=1))[:, None] * wn[None, :]
+        err = np.abs(proj.astype(np.float64) - v)
+        ratio = np.max(err / np.maximum(scale, 1e-300))
+        worst = max(worst, float(ratio))
+        trusted = np.abs(proj) > gamma * scale + tau_abs
+        assert np.all(np.sign(proj[trusted]) == np.sign(v[trusted]))
+        log("mfma error: max ratio", ratio, "gamma", gamma, "trusted", trusted.mean())
+    assert worst < gamma / 2, (worst, gamma)
+
+
 @pytest.mark.parametrize("family", [2, 3])
 @pytest.mark.parametrize("K,L,b,mean", [(1, 1, 1, 3), (2, 32, 20, 81), (3, 48, 22, 68),
                                         (4, 5, 12, 300), (1, 200, 16, 10), (7, 3, 24, 1000)])
@@ -194,8 +277,9 @@ def test_c4_grid_u32_cells_large_lds(fl):
 
 
 def test_c2_genome_hashed_filter(fl):
-    """N = 40 000 > 2^15: the decode's membership bitmaps are hashed (false
-    positives possible, resolved by the exact group gather)."""
+    """N = 40 000 (over 2^15 points, B = 164): larger cells than the other
+    scaled genome index, so a decode pass streams several 256-member chunks
+    per cell and the per-lane sorted insertion sees long runs of members."""
     cfg, (it, of), (qit, qof), _ = scaled("c2", 0.04, 100)
     _check_all(fl, 3, (it, of), (qit, qof), cfg["K"], cfg["L"], cfg["R"], cfg["B"], 9,
                cfg["bucket_bits"], ks=(1, 10, 64))
@@ -204,8 +288,8 @@ def test_c2_genome_hashed_filter(fl):
 @pytest.mark.parametrize("R", [2, 5])
 def test_many_positive_cells_chunked(fl, R):
     """One 1-bit table: about half of all cells are positive, more than the
-    decode's single-scan cell list holds, so cells are streamed 256 at a
-    time (with and without membership bitmaps)."""
+    decode's positive-cell list holds in one round, so a pass collects and
+    streams the cells of its repetition in several rounds."""
     X, Q, _ = synth.dense_gmm(N=20000, d=8, n_centres=50, nq=40)
     gi, oi = build_both(fl, 0, X, 1, 1, R, 2000, 23, 0)
     for k in (1, 10, 64):

@@ -54,8 +54,10 @@ def _bind(L):
         "or_build_lists": (i64, [vp, vp, u64, u32, u32, u32, u32, vp, vp, u64]),
         "or_counts": (None, [vp, vp, u32, u32, u32, vp, u64, vp]),
         "or_counts_brute": (None, [vp, vp, u64, u32, u32, u32, vp, u64, vp]),
-        "or_decode_alg3": (None, [vp, vp, vp, u64, u32, u32, u32, vp, vp]),
-        "or_decode_closed": (None, [vp, vp, u64, u32, u32, u32, vp, vp]),
+        "or_decode": (None, [vp, vp, u64, u32, u32, u32, vp, vp]),
+        "or_query_many": (None, [vp, vp, u32, u32, vp, u64, u32, u32, vp, u64, u32, vp, vp]),
+        "or_set_threads": (None, [ctypes.c_int]),
+        "or_get_threads": (ctypes.c_int, []),
         "or_query_fixed_t": (None, [vp, vp, u64, u32, u32, u32, vp]),
     }
     for name, (res, args) in sig.items():
@@ -183,26 +185,25 @@ def counts_brute(codes, g, B, qcodes):
     return out
 
 
-def decode_alg3(cnt, mem_off, mem, B, k):
-    """Algorithm 3 (threshold relaxation), walked literally."""
-    cnt = np.ascontiguousarray(cnt, dtype=np.uint8)
-    R, N = mem.shape
-    ids = np.empty(k, dtype=np.uint32)
-    sc = np.empty(k, dtype=np.uint32)
-    lib().or_decode_alg3(_p(cnt), _p(mem_off), _p(mem), N, R, B, k, _p(ids),
-                         _p(sc))
-    return ids, sc
-
-
-def decode_closed(cnt, g, B, k):
-    """Same output as decode_alg3 from the (-m, c*, id) key order."""
+def decode(cnt, g, B, k):
+    """Algorithm 3 (threshold relaxation) of one query's cell counts: the k
+    smallest keys (-m(x), c*(x), x), ids and scores (m(x))."""
     cnt = np.ascontiguousarray(cnt, dtype=np.uint8)
     g = np.ascontiguousarray(g, dtype=np.uint32)
     R, N = g.shape
     ids = np.empty(k, dtype=np.uint32)
     sc = np.empty(k, dtype=np.uint32)
-    lib().or_decode_closed(_p(cnt), _p(g), N, R, B, k, _p(ids), _p(sc))
+    lib().or_decode(_p(cnt), _p(g), N, R, B, k, _p(ids), _p(sc))
     return ids, sc
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (1 for a one-core baseline)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().or_get_threads())
 
 
 def query_fixed_t(cnt, g, B, t):
@@ -238,7 +239,6 @@ class OracleIndex:
             self.N = len(offs) - 1
             self.codes = minhash_codes(items, offs, seed, K, L, bucket_bits)
         self.g = groups(self.N, R, B, seed)
-        self.mem_off, self.mem = members(self.g, B)
         self.offsets, self.cells = build_lists(self.codes, self.g, B, self.nbits)
 
     def _dense(self, data):
@@ -256,17 +256,18 @@ class OracleIndex:
         return counts(self.offsets, self.cells, qcodes, self.R * self.B,
                       self.nbits)
 
-    def query(self, q, k, literal=True):
-        """Full query: hash, count through the reverse index, relax."""
-        qc = self.hash(q)
-        cnt = self.counts(qc)
-        nq = cnt.shape[0]
+    def query(self, q, k):
+        """Full query: hash, count through the reverse index, relax
+        (Algorithm 3), queries spread over the oracle's threads."""
+        return self.query_codes(self.hash(q), k)
+
+    def query_codes(self, qc, k):
+        qc = np.ascontiguousarray(qc, dtype=np.uint32)
+        nq = qc.shape[0]
         ids = np.empty((nq, k), dtype=np.uint32)
         sc = np.empty((nq, k), dtype=np.uint32)
-        for i in range(nq):
-            if literal:
-                ids[i], sc[i] = decode_alg3(cnt[i], self.mem_off, self.mem,
-                                            self.B, k)
-            else:
-                ids[i], sc[i] = decode_closed(cnt[i], self.g, self.B, k)
+        cells = self.cells if self.cells.size else np.zeros(1, dtype=np.uint32)
+        g = np.ascontiguousarray(self.g, dtype=np.uint32)
+        lib().or_query_many(_p(self.offsets), _p(cells), self.L, self.nbits, _p(g), self.N,
+                            self.R, self.B, _p(qc), nq, k, _p(ids), _p(sc))
         return ids, sc

@@ -19,6 +19,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------- */
 /* Counter-based generator: the output function of SplitMix64 (Steele, Lea and
@@ -341,67 +344,60 @@ void or_counts_brute(const uint32_t *codes, const uint32_t *g, uint64_t N,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Threshold relaxation (Algorithm 3), literally: cells sorted by descending
- * count (ties: ascending cell id), each cell's members walked in ascending id;
- * a point is reported when its walk counter reaches R, with score = the count
- * of the cell that completed it; stop at k.  Missing results (k > N) are
- * padded with id 0xFFFFFFFF and score 0.                                     */
-void or_decode_alg3(const uint8_t *counts, const uint64_t *mem_off,
-                    const uint32_t *mem, uint64_t N, uint32_t R, uint32_t B,
-                    uint32_t k, uint32_t *ids, uint32_t *scores)
-{
-    const uint32_t ncells = R * B;
-    /* order cells: counting sort on count (descending), stable in cell id */
-    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * ncells);
-    uint32_t nbin[257];
-    memset(nbin, 0, sizeof(nbin));
-    for (uint32_t c = 0; c < ncells; ++c) nbin[255 - counts[c] + 1]++;
-    for (int v = 0; v < 256; ++v) nbin[v + 1] += nbin[v];
-    for (uint32_t c = 0; c < ncells; ++c) order[nbin[255 - counts[c]]++] = c;
-
-    uint32_t *walk = (uint32_t *)calloc(N ? N : 1, sizeof(uint32_t));
-    uint32_t nres = 0;
-    for (uint32_t i = 0; i < ncells && nres < k; ++i) {
-        uint32_t c = order[i], r = c / B, b = c % B;
-        const uint64_t *off = mem_off + (uint64_t)r * (B + 1);
-        const uint32_t *m = mem + (uint64_t)r * N;
-        for (uint64_t p = off[b]; p < off[b + 1]; ++p) {
-            uint32_t x = m[p];
-            if (++walk[x] == R) {
-                ids[nres] = x;
-                scores[nres] = counts[c];
-                if (++nres == k) break;
-            }
-        }
-    }
-    for (uint32_t i = nres; i < k; ++i) {
-        ids[i] = 0xFFFFFFFFu;
-        scores[i] = 0;
-    }
-    free(walk);
-    free(order);
-}
-
-/* Closed form of the same output: with m(x) = min_r C[r*B + g_r(x)] and
- * c*(x) = the largest cell id among x's cells whose count equals m(x), the
- * relaxation reports points in increasing (-m(x), c*(x), x).  Written
- * independently of the walk above so each pins the other.                  */
+/* Threshold relaxation (Algorithm 3; Section 6 states it is Algorithm 2 run
+ * with decreasing thresholds until k points are reported).
+ *
+ * What it reports, from the definitions: a point x is reported once the
+ * relaxation has passed all R of its cells, i.e. at threshold
+ * m(x) = min_r C[r*B + g_r(x)] (Algorithm 2 at t reports exactly the points
+ * with m(x) >= t), and its score is that threshold (reading A10).  Cells are
+ * passed in descending count, equal counts by ascending cell id (A2), and the
+ * points of one cell by ascending id (A3), so among the points reported at
+ * the same threshold, x comes after every point whose last cell precedes
+ * x's last cell c*(x) = the largest cell id among x's cells of count m(x),
+ * and after the smaller ids of that same cell.  The output is therefore the k
+ * smallest keys (-m(x), c*(x), x), in increasing order; missing results
+ * (k > N) are padded with id 0xFFFFFFFF and score 0.
+ *
+ * The key of every point is computed, and the k smallest are kept in a
+ * bounded max-heap (a partial sort), then emitted in increasing order.     */
 typedef struct { uint32_t negm, cstar, x; } or_key;
 
-static int or_cmp_key(const void *a, const void *b)
+static int or_key_less(const or_key *p, const or_key *q)
 {
-    const or_key *p = (const or_key *)a, *q = (const or_key *)b;
-    if (p->negm != q->negm) return p->negm < q->negm ? -1 : 1;
-    if (p->cstar != q->cstar) return p->cstar < q->cstar ? -1 : 1;
-    if (p->x != q->x) return p->x < q->x ? -1 : 1;
-    return 0;
+    if (p->negm != q->negm) return p->negm < q->negm;
+    if (p->cstar != q->cstar) return p->cstar < q->cstar;
+    return p->x < q->x;
 }
 
-void or_decode_closed(const uint8_t *counts, const uint32_t *g, uint64_t N,
-                      uint32_t R, uint32_t B, uint32_t k, uint32_t *ids,
-                      uint32_t *scores)
+static void or_heap_down(or_key *h, uint32_t n, uint32_t i)
 {
-    or_key *keys = (or_key *)malloc(sizeof(or_key) * (N ? N : 1));
+    for (;;) {
+        uint32_t l = 2 * i + 1, r = l + 1, big = i;
+        if (l < n && or_key_less(&h[big], &h[l])) big = l;
+        if (r < n && or_key_less(&h[big], &h[r])) big = r;
+        if (big == i) return;
+        or_key t = h[i]; h[i] = h[big]; h[big] = t;
+        i = big;
+    }
+}
+
+static void or_heap_up(or_key *h, uint32_t i)
+{
+    while (i > 0) {
+        uint32_t p = (i - 1) / 2;
+        if (!or_key_less(&h[p], &h[i])) return;
+        or_key t = h[i]; h[i] = h[p]; h[p] = t;
+        i = p;
+    }
+}
+
+/* heap: scratch of k keys. */
+static void or_decode_keys(const uint8_t *counts, const uint32_t *g, uint64_t N,
+                           uint32_t R, uint32_t B, uint32_t k, uint32_t *ids,
+                           uint32_t *scores, or_key *heap)
+{
+    uint32_t n = 0;
     for (uint64_t x = 0; x < N; ++x) {
         uint32_t m = 0xFFFFFFFFu, cs = 0;
         for (uint32_t r = 0; r < R; ++r) {
@@ -412,21 +408,76 @@ void or_decode_closed(const uint8_t *counts, const uint32_t *g, uint64_t N,
                 cs = c;
             }
         }
-        keys[x].negm = 1000u - m;
-        keys[x].cstar = cs;
-        keys[x].x = (uint32_t)x;
-    }
-    qsort(keys, N, sizeof(or_key), or_cmp_key);
-    for (uint32_t i = 0; i < k; ++i) {
-        if (i < N) {
-            ids[i] = keys[i].x;
-            scores[i] = 1000u - keys[i].negm;
-        } else {
-            ids[i] = 0xFFFFFFFFu;
-            scores[i] = 0;
+        or_key key = {1000u - m, cs, (uint32_t)x};
+        if (n < k) {
+            heap[n] = key;
+            or_heap_up(heap, n);
+            ++n;
+        } else if (or_key_less(&key, &heap[0])) {
+            heap[0] = key;
+            or_heap_down(heap, n, 0);
         }
     }
-    free(keys);
+    /* pop the largest to the back: increasing order */
+    for (uint32_t i = n; i > 0; --i) {
+        ids[i - 1] = heap[0].x;
+        scores[i - 1] = 1000u - heap[0].negm;
+        heap[0] = heap[i - 1];
+        or_heap_down(heap, i - 1, 0);
+    }
+    for (uint32_t i = n; i < k; ++i) {
+        ids[i] = 0xFFFFFFFFu;
+        scores[i] = 0;
+    }
+}
+
+void or_decode(const uint8_t *counts, const uint32_t *g, uint64_t N, uint32_t R,
+               uint32_t B, uint32_t k, uint32_t *ids, uint32_t *scores)
+{
+    or_key *heap = (or_key *)malloc(sizeof(or_key) * (k ? k : 1));
+    or_decode_keys(counts, g, N, R, B, k, ids, scores, heap);
+    free(heap);
+}
+
+/* Whole queries from their bucket codes: counts through the reverse index
+ * (or_counts) then the decode above, one query per thread.               */
+void or_query_many(const uint64_t *offsets, const uint32_t *cells, uint32_t L,
+                   uint32_t nbits, const uint32_t *g, uint64_t N, uint32_t R,
+                   uint32_t B, const uint32_t *qcodes, uint64_t nq, uint32_t k,
+                   uint32_t *ids, uint32_t *scores)
+{
+#pragma omp parallel
+    {
+        uint8_t *C = (uint8_t *)malloc((size_t)R * B);
+        or_key *heap = (or_key *)malloc(sizeof(or_key) * (k ? k : 1));
+#pragma omp for schedule(dynamic, 4)
+        for (uint64_t q = 0; q < nq; ++q) {
+            or_counts(offsets, cells, L, nbits, R * B, qcodes + q * L, 1, C);
+            or_decode_keys(C, g, N, R, B, k, ids + q * k, scores + q * k, heap);
+        }
+        free(heap);
+        free(C);
+    }
+}
+
+/* Thread count of the parallel loops (a baseline timed on one core sets 1;
+ * changes no result). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int or_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Fixed-threshold query (Algorithm 2): a cell is positive when its count is

@@ -26,7 +26,7 @@ def build_both(flinng, family, data, K, L, R, B, seed, bucket_bits=0):
 
 
 def oracle_query(oi, q, k):
-    return oi.query(q, k, literal=True)
+    return oi.query(q, k)
 
 
 def scaled(name, scale, nq, **over):

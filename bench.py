@@ -1,23 +1,24 @@
 #!/usr/bin/env python
-"""FLINNG batched-query benchmark on one MI355X.
+"""FLINNG query path on one MI355X: benchmark.
 
-One step = one pass of the query path over a batch of queries that is
-already resident in HBM: hash (MinHash or SRP) -> per-cell counts through the
-reverse index -> threshold relaxation decode -> top-k ids/scores.  The default
-workload is the 1M-read genome set (MinHash K=2, L=32, R=4, B=4096, 20-bit
-buckets, 10 000 queries, k=10).  Prints one JSON line.
+Default (--workload c5): the genome-read index (1M sets, MinHash) and the
+ReLU-embedding index (1M x 4096 bf16, SRP) resident together, both at the
+fastest (K, L) of their sweeps that reaches R1@10 >= 0.9 (--fixed: as
+configured).  One step serves the whole mixed query set -- 10,000 genome
+reads and 10,000 embeddings, in requests of U{1..512} queries, families
+interleaved at random -- through the continuous-batching server, with the
+queries already in HBM and the answers written to HBM; `value` is that
+served rate.  The same line carries the plain batched rates (each family's
+query set as one batch, and both back to back), the served rate of the same
+requests from host memory (PCIe included), a sweep of Poisson arrival rates
+with p50/p99 latency, recall against exact neighbours, per-stage times, the
+rooflines of the query kernels, the SRP projection and the builds, and the
+CPU oracle timed on the host cores.
 
-Extras on the same line: index build time, per-stage times, the decode
-kernel's roofline (algorithmic bytes from the kernel's own work counters /
-its event-timed launch duration, against 8 TB/s), recall@10 against exact
-Jaccard / cosine neighbours on a query sample, the served (continuous
-batching) rate with p50/p99 latency under a burst and under open-loop Poisson
-arrivals, and the CPU oracle timed on one host core over a bounded query
-sample.
-
---workload c5 keeps the genome and ReLU-embedding indexes resident together
-and sweeps Poisson arrival rates of mixed-family requests (1..512 queries
-each) through the server, beside each family's plain batched rate.
+--workload c1|c2|c3|c4: one index, plain batched (`value`), with its
+stages, roofline, recall, serving and oracle baseline.  --pareto: the
+(K, L) sweep.  --mfma-error: the accuracy of the bf16 matrix-core
+projections against FP64 on the ReLU workload.
 """
 import argparse
 import ctypes
@@ -32,7 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 COPY_BYTES = 1 << 30
+METRIC = "queries/s at recall@10>=0.9, served vs plain batched; p50/p99 query latency"
 
 
 def log(*a):
@@ -43,23 +46,28 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-sweep", action="store_true", help="c5: skip the Poisson sweep")
+    ap.add_argument("--cpu-seconds", type=float, default=5.0,
+                    help="oracle time per family and thread setting")
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (a plain copy of known "
                          "size, for scaling the HBM byte counters of a profiled run)")
     ap.add_argument("--fixed", action="store_true",
-                    help="use the workload's configured (K, L) even where a tuned setting exists")
+                    help="use the workloads' configured (K, L) even where a tuned setting exists")
     ap.add_argument("--pareto", action="store_true",
                     help="sweep (K, L) around the workload's and report the fastest setting "
                          "reaching R1@10 >= 0.9")
+    ap.add_argument("--mfma-error", action="store_true",
+                    help="measure |v32 - v| / (|x| |w|) of the bf16 projections on the ReLU "
+                         "workload (all queries and a sample of indexed rows)")
     ap.add_argument("--rates", default="", help="comma-separated Poisson arrival rates (queries/s)")
     return ap.parse_args()
 
@@ -78,6 +86,20 @@ def to_dev(torch, a):
     return t.cuda()
 
 
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "cpu_model": model}
 
 
 class Workload:
@@ -112,8 +134,12 @@ class Workload:
         self.data_d = data_d if keep_data else None
         del data_d
         info = self.index.info
-        log(f"built index in {self.build_s:.2f}s: entries={info.list_entries} "
-            f"bytes={info.device_bytes / 2**20:.1f}MiB")
+        log(f"built {c['name']} (K={self.K}, L={self.L}) in {self.build_s:.2f}s: "
+            f"entries={info.list_entries} bytes={info.device_bytes / 2**20:.1f}MiB")
+
+    @property
+    def name(self):
+        return self.cfg["name"]
 
     def host_slice(self, p, n):
         """Queries p..p+n-1 as a host batch (rows, or items + rebased offsets)."""
@@ -124,8 +150,27 @@ class Workload:
         o = of[p:p + n + 1]
         return (it[int(o[0]):int(o[-1])], (o - o[0]).astype(np.uint64))
 
+    def build_roofline(self):
+        """Build inserts: N*L*R (bucket, cell) tuples, each read and written
+        once per 8-bit radix pass of its sort (8-byte keys)."""
+        R, L, N = self.R, self.L, self.cfg["N"]
+        cb = 1
+        while (1 << cb) < R * ((self.B + 3) & ~3):
+            cb += 1
+        bits = (self.K if self.dense else self.b) + cb
+        passes = (bits + 7) // 8
+        tuples = N * L * R
+        byts = tuples * passes * 16
+        gbs = byts / self.build_s / 1e9
+        return {"kernel": "index build (hash, groups, per-table radix sort, dedup, CSR)",
+                "workload": self.name, "bound": "hbm", "tuples": tuples, "sort_passes": passes,
+                "alg_bytes": byts, "build_s": round(self.build_s, 4),
+                "tuples_per_s": round(tuples / self.build_s, 1),
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
-def plain(w, torch, steps, warmup, persistent):
+
+def plain(w, torch, steps, warmup, persistent=False):
     """Event-timed plain batched steps over the device-resident queries."""
     import numpy as np
     dev = torch.device("cuda:0")
@@ -195,16 +240,29 @@ def stages(w, torch, fl, steps, persistent, out):
     cb = w.index.info.cell_id_bytes
     alg = w.nq * w.L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * w.R + w.nq * w.k * 8
     ach = alg / (decode_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "kernel": "query_kernel (count + threshold + decode)",
+    roof = {"kernel": "query_kernel (count + threshold + decode)", "workload": w.name,
+            "K": w.K, "L": w.L, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled; "
+                            "read from the committed counter summary for this kernel source)",
             "alg_bytes_per_launch": int(alg), "launch_ms": round(decode_ms, 4),
             "list_entries": st[0], "member_ids_all_passes": st[1], "member_ids_final": st[2],
             "passes": st[3], "group_rows_gathered": st[4]}
-    log(f"hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg / 1e6:.1f} MB -> "
+    out = {"hash_ms": hash_ms, "decode_ms": decode_ms, "query_roofline": roof}
+    if w.dense:
+        # the hash stage (norms, bf16 MFMA projection, FP64 recheck, pack)
+        # against the dense bf16 matrix-core peak: a lower bound on the
+        # projection kernel's own utilisation
+        flops = 2.0 * w.nq * w.cfg["d"] * w.K * w.L
+        tf = flops / (hash_ms / 1e3) / 1e12
+        out["hash_roofline"] = {
+            "kernel": "SRP hash stage (prep + srp_mfma_lds_kernel + recheck/pack)",
+            "workload": w.name, "K": w.K, "L": w.L, "bound": "mfma", "achieved": round(tf, 2),
+            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+            "alg_flops_per_launch": flops, "launch_ms": round(hash_ms, 4), "traffic": None}
+    log(f"{w.name}: hash {hash_ms:.3f} ms, decode {decode_ms:.3f} ms, alg {alg / 1e6:.1f} MB -> "
         f"{ach:.0f} GB/s; stats {st}")
-    return hash_ms, decode_ms, roof
+    return out
 
 
 def measured_traffic(w):
@@ -230,97 +288,218 @@ def recall(w, fl, ids, nq_sample):
     t = time.time()
     ns = min(nq_sample, w.nq)
     if w.dense:
-        ti, _ = truth.cosine_topk_gpu(w.data, w.queries[:ns], 10, dense_bf16=(w.fam == fl.SRP_BF16))
+        ti, _ = truth.cosine_topk_gpu(w.data, w.queries[:ns], 10, dense_bf16=(w.fam == fl.SRP_BF16),
+                                      X_dev=w.data_d)
     else:
         ji = truth.JaccardIndex(w.data[0], w.data[1])
         ti, _ = ji.topk(w.queries[0], w.queries[1][:ns + 1], 10)
     r1 = truth.recall_at(ids[:ns, :10], ti[:, 0])
-    log(f"R1@10 = {r1:.4f} on {ns} queries ({time.time() - t:.1f}s)")
+    log(f"{w.name}: R1@10 = {r1:.4f} on {ns} queries ({time.time() - t:.1f}s)")
     return {"R1@10": round(r1, 4), "queries": ns}
 
 
-def sweep_requests(w, sizes):
-    """Requests (slot 0, batch, size, first query) covering the whole query
-    set in order, with the given sizes (cycled) or U{1..512}."""
+# ---------------------------------------------------------------------------
+# serving
+
+def mixed_requests(ws, seed, sizes=None):
+    """Requests (slot, first query, size) covering every workload's query set
+    exactly once, sizes U{1..512} (or `sizes`, cycled), the families
+    interleaved in a seeded random order."""
     import numpy as np
-    rng = np.random.default_rng(4)
-    out, pos, i = [], 0, 0
-    while pos < w.nq:
-        n = int(sizes[i % len(sizes)]) if sizes is not None else int(rng.integers(1, 513))
-        n = min(n, w.nq - pos)
-        out.append((0, w.host_slice(pos, n), n, pos))
-        pos += n
-        i += 1
+    rng = np.random.default_rng(seed)
+    per = []
+    for s, w in enumerate(ws):
+        lst, pos, i = [], 0, 0
+        while pos < w.nq:
+            n = int(sizes[i % len(sizes)]) if sizes is not None else int(rng.integers(1, 513))
+            n = min(n, w.nq - pos)
+            lst.append((s, pos, n))
+            pos += n
+            i += 1
+        per.append(lst)
+    slots = np.concatenate([np.full(len(p), s) for s, p in enumerate(per)])
+    rng.shuffle(slots)
+    nxt = [0] * len(ws)
+    out = []
+    for s in slots:
+        out.append(per[s][nxt[s]])
+        nxt[s] += 1
     return out
 
 
-def poisson_requests(workloads, n_req, seed, sizes=None):
-    """n_req requests (slot, batch, size, first query): the slot uniform over
-    the workloads, the size U{1..512} unless `sizes` is given (cycled); each
-    workload's queries are taken in order, wrapping around."""
+def random_requests(ws, n_req, seed):
+    """n_req requests (slot, first query, size): slot uniform, size
+    U{1..512}, each workload's queries taken in order, wrapping around."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    pos = [0] * len(workloads)
+    pos = [0] * len(ws)
     out = []
-    for i in range(n_req):
-        s = int(rng.integers(0, len(workloads))) if len(workloads) > 1 else 0
-        w = workloads[s]
-        n = int(sizes[i % len(sizes)]) if sizes is not None else int(rng.integers(1, 513))
-        n = min(n, w.nq)
-        if pos[s] + n > w.nq:
+    for _ in range(n_req):
+        s = int(rng.integers(0, len(ws)))
+        n = min(int(rng.integers(1, 513)), ws[s].nq)
+        if pos[s] + n > ws[s].nq:
             pos[s] = 0
-        out.append((s, w.host_slice(pos[s], n), n, pos[s]))
+        out.append((s, pos[s], n))
         pos[s] += n
     return out
 
 
-def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False, submitters=1):
-    """Submit `reqs` to a fresh server (after a warm-up burst of the first 64),
-    open loop: exponential inter-arrival gaps with mean (mean request size /
-    rate_qps), or all at once when rate_qps is 0.  `submitters` client
-    threads share the arrivals round-robin (the library copies a request's
-    payload inside the submit call, outside the Python lock, so they copy in
-    parallel); one more thread waits for the tickets.  Returns the achieved
-    rate (queries / time from first arrival to last completion), the server's
-    latency percentiles (completion - submit) and whether every result equals
-    the plain batched result for the same queries."""
+class DeviceRequests:
+    """Requests marshalled once for the device path: inputs are slices of
+    the device-resident query sets (dense rows; set items on the device with
+    their offsets on the host), results go to slices of device tensors."""
+
+    def __init__(self, fl, torch, ws, reqs):
+        import numpy as np
+        self.fl, self.ws, self.reqs = fl, ws, reqs
+        self.outs = [(torch.empty((w.nq, w.k), dtype=torch.int32, device="cuda"),
+                      torch.empty((w.nq, w.k), dtype=torch.int32, device="cuda")) for w in ws]
+        self.inputs, self.ptrs, self.keep = [], [], []
+        for s, p, n in reqs:
+            w = ws[s]
+            inp = fl.Input()
+            if w.dense:
+                esz = 4 if w.fam == fl.SRP_F32 else 2
+                inp.values = w.q_d.data_ptr() + p * w.cfg["d"] * esz
+                inp.on_device = 1
+            else:
+                of = np.ascontiguousarray(w.queries[1][p:p + n + 1], dtype=np.uint64)
+                self.keep.append(of)
+                inp.values = w.q_d[0].data_ptr()
+                inp.offsets = of.ctypes.data
+                inp.on_device = 2
+            inp.count = n
+            ids_t, sc_t = self.outs[s]
+            self.inputs.append(inp)
+            self.ptrs.append((ids_t.data_ptr() + p * w.k * 4, sc_t.data_ptr() + p * w.k * 4, w.k))
+
+    def submit(self, srv_h, i):
+        t = ctypes.c_uint64()
+        s = self.reqs[i][0]
+        ip, sp, k = self.ptrs[i]
+        rc = self.fl.lib().flinng_serve_submit_to(srv_h, s, ctypes.byref(self.inputs[i]), k, ip, sp,
+                                                  ctypes.byref(t))
+        self.fl.check(rc)
+        return t.value
+
+    def wait(self, srv_h, ticket):
+        self.fl.check(self.fl.lib().flinng_serve_wait(srv_h, ticket, None, None, -1))
+
+
+def make_server(fl, ws, persistent=False):
+    return fl.Server([w.index for w in ws], mem_budget=8 << 30, max_inflight=4,
+                     max_batch=4096, persistent=persistent)
+
+
+def served_device_steps(fl, torch, ws, reqs, steps, warmup, refs):
+    """The timed serving step: submit every request of one mixed query set
+    (device inputs, device outputs) and wait for all; `steps` of them after
+    `warmup`, bracketed by device synchronisation."""
     import numpy as np
-    rng = np.random.default_rng(seed)
+    dr = DeviceRequests(fl, torch, ws, reqs)
+    srv = make_server(fl, ws)
+    h = srv._h
+
+    def one():
+        tickets = [dr.submit(h, i) for i in range(len(reqs))]
+        for t in tickets:
+            dr.wait(h, t)
+
+    try:
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    same = True
+    for (ids_t, sc_t), (ri, rs) in zip(dr.outs, refs):
+        same &= bool(np.array_equal(ids_t.cpu().numpy().view(np.uint32), ri) and
+                     np.array_equal(sc_t.cpu().numpy().view(np.uint32), rs))
+    nq = sum(r[2] for r in reqs)
+    ms = wall * 1e3 / steps
+    return {"ms_per_step": round(ms, 4), "achieved_qps": round(nq / (ms / 1e3), 1),
+            "queries_per_step": nq, "requests_per_step": len(reqs),
+            "batches": st["batches"], "mean_batch": round(st["mean_batch"], 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "latency_requests": st["completed"], "identical_to_plain": same,
+            "inputs": "device (HBM)", "outputs": "device (HBM)"}
+
+
+def served_host_burst(fl, ws, reqs, refs, reps=3):
+    """The same requests from host memory (copied at submit, results copied
+    back): the PCIe-inclusive served rate, best of `reps` bursts."""
+    import numpy as np
+    batches = [(s, ws[s].host_slice(p, n), n, p) for s, p, n in reqs]
+    srv = make_server(fl, ws)
+    best, same, st = None, True, None
+    try:
+        for _ in range(reps):
+            srv.reset_stats()
+            t0 = time.perf_counter()
+            tickets = [(srv.submit(s, q, ws[s].k), s, p) for s, q, n, p in batches]
+            res = [(srv.wait(t, n, ws[s].k), s, p) for (t, n), s, p in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            best = wall if best is None else min(best, wall)
+        for (ids, sc), s, p in res:
+            n = ids.shape[0]
+            same &= bool(np.array_equal(ids, refs[s][0][p:p + n]) and
+                         np.array_equal(sc, refs[s][1][p:p + n]))
+    finally:
+        srv.close()
+    nq = sum(r[2] for r in reqs)
+    return {"achieved_qps": round(nq / best, 1), "ms_per_burst": round(best * 1e3, 3),
+            "queries": nq, "requests": len(reqs), "batches": st["batches"],
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "identical_to_plain": same, "inputs": "host (copied at submit, over PCIe)",
+            "outputs": "host"}
+
+
+def poisson_point(fl, torch, ws, rate, n_req, seed, refs):
+    """Open-loop Poisson arrivals of device requests at `rate` queries/s: a
+    submitter thread issues each request at its arrival time, a waiter thread
+    completes them in order; latency = completion - submit (the server's
+    host clock)."""
+    import numpy as np
+    reqs = random_requests(ws, n_req, seed)
+    dr = DeviceRequests(fl, torch, ws, reqs)
+    rng = np.random.default_rng(seed + 1)
     mean = float(np.mean([r[2] for r in reqs]))
-    arrivals = (np.cumsum(rng.exponential(mean / rate_qps, len(reqs))) if rate_qps > 0
-                else np.zeros(len(reqs)))
-    srv = fl.Server([w.index for w in workloads], mem_budget=8 << 30, max_inflight=4,
-                    max_batch=4096, persistent=persistent)
-    # warm-up: one burst sizes every stream's workspace and the payload pool;
-    # statistics restart after it so that they describe the steady state
-    warm = [srv.submit(r[0], r[1], workloads[r[0]].k) + (workloads[r[0]].k,) for r in reqs[:64]]
-    for tk, n, k in warm:
-        srv.wait(tk, n, k)
-    srv.reset_stats()
+    arrivals = np.cumsum(rng.exponential(mean / rate, len(reqs)))
+    srv = make_server(fl, ws)
+    h = srv._h
     tq = queue.Queue()
-    state = {"same": True, "t_last": 0.0, "err": None, "lag": 0.0}
-    lock = threading.Lock()
+    state = {"err": None, "lag": 0.0, "t_last": 0.0}
+    try:
+        for i in range(min(32, len(reqs))):        # warm-up: workspaces, pools
+            dr.wait(h, dr.submit(h, i))
+        torch.cuda.synchronize()
+        srv.reset_stats()
 
-    def waiter():
-        try:
-            while True:
-                item = tq.get()
-                if item is None:
-                    return
-                tk, n, k, (s, _, _, p) = item
-                ids, sc = srv.wait(tk, n, k)
-                state["t_last"] = time.perf_counter()
-                ref_i, ref_s = refs[s]
-                state["same"] &= bool(np.array_equal(ids, ref_i[p:p + n]) and
-                                      np.array_equal(sc, ref_s[p:p + n]))
-        except Exception as e:  # surfaced after join
-            state["err"] = e
+        def waiter():
+            try:
+                while True:
+                    t = tq.get()
+                    if t is None:
+                        return
+                    dr.wait(h, t)
+                    state["t_last"] = time.perf_counter()
+            except Exception as e:  # noqa: BLE001
+                state["err"] = e
 
-    def submitter(j, t0):
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter() + 0.005
+        lag = 0.0
         try:
-            lag = 0.0
-            for i in range(j, len(reqs), submitters):
-                r = reqs[i]
+            for i in range(len(reqs)):
                 target = t0 + arrivals[i]
                 now = time.perf_counter()
                 while now < target:
@@ -328,67 +507,146 @@ def serve_run(fl, workloads, reqs, rate_qps, seed, refs, persistent=False, submi
                         time.sleep(target - now - 0.001)
                     now = time.perf_counter()
                 lag = max(lag, now - target)
-                k = workloads[r[0]].k
-                tk, n = srv.submit(r[0], r[1], k)
-                tq.put((tk, n, k, r))
-            with lock:
-                state["lag"] = max(state["lag"], lag)
-        except Exception as e:
-            state["err"] = e
-
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.perf_counter() + 0.01
-    subs = [threading.Thread(target=submitter, args=(j, t0)) for j in range(submitters)]
-    for t in subs:
-        t.start()
-    for t in subs:
-        t.join()
-    tq.put(None)
-    th.join()
-    if state["err"] is not None:
-        raise state["err"]
-    wall = state["t_last"] - t0
-    st = srv.stats()
-    srv.close()
+                tq.put(dr.submit(h, i))
+        finally:
+            tq.put(None)
+            th.join()
+        if state["err"] is not None:
+            raise state["err"]
+        st = srv.stats()
+    finally:
+        srv.close()
+    same = True
+    for (ids_t, sc_t), w, (ri, rs) in zip(dr.outs, ws, refs):
+        ids = ids_t.cpu().numpy().view(np.uint32)
+        sc = sc_t.cpu().numpy().view(np.uint32)
+        for s, p, n in reqs:
+            if ws[s] is w:
+                same &= bool(np.array_equal(ids[p:p + n], ri[p:p + n]) and
+                             np.array_equal(sc[p:p + n], rs[p:p + n]))
     nq = sum(r[2] for r in reqs)
-    return {"offered_qps": rate_qps if rate_qps > 0 else "burst",
-            "achieved_qps": round(nq / wall, 1), "p50_ms": round(st["p50_ms"], 3),
-            "p99_ms": round(st["p99_ms"], 3), "requests": len(reqs), "queries": nq,
+    wall = state["t_last"] - t0
+    return {"offered_qps": rate, "achieved_qps": round(nq / wall, 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "max_ms": round(st["max_ms"], 3), "requests": st["completed"], "queries": nq,
             "batches": st["batches"], "mean_batch": round(st["mean_batch"], 1),
-            "max_submit_lag_ms": round(state["lag"] * 1e3, 3), "submitters": submitters,
-            "identical_to_plain": bool(state["same"])}
+            "max_submit_lag_ms": round(float(lag) * 1e3, 3), "identical_to_plain": same}
 
 
-def cpu_baseline(w, ids, sc, seconds):
-    """The oracle on one host core over the first queries of the batch."""
+def poisson_sweep(fl, torch, ws, rates, refs):
+    out = []
+    for i, rate in enumerate(rates):
+        # about 4 s of arrivals per point, and at least 2,000 requests from
+        # 100k queries/s up
+        n_req = int(rate * 4.0 / 256.5)
+        if rate >= 1e5:
+            n_req = max(n_req, 2000)
+        n_req = max(16, min(n_req, 8000))
+        r = poisson_point(fl, torch, ws, rate, n_req, 300 + i, refs)
+        log(f"served Poisson @ {rate:,.0f} q/s: {r}")
+        out.append(r)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle baseline
+
+def _oracle_time(oi, w, seconds, batch, hash_fn=None):
+    """Oracle queries (hash, counts, Algorithm 3) over the first queries, in
+    batches, until `seconds` have passed; returns (queries, seconds, ids, scores)."""
+    import numpy as np
+    done, ids, sc = 0, [], []
+    t0 = time.perf_counter()
+    while done < w.nq and time.perf_counter() - t0 < seconds:
+        n = min(batch, w.nq - done)
+        i, s = oi.query(w.host_slice(done, n), w.k)
+        ids.append(i)
+        sc.append(s)
+        done += n
+    el = time.perf_counter() - t0
+    return done, el, np.concatenate(ids), np.concatenate(sc)
+
+
+def cpu_baseline_mixed(ws, refs, seconds, relu_points=20000):
+    """The oracle timed on the host: the genome queries against the oracle's
+    own full 1M-read index; the embedding queries against an oracle index of
+    the first `relu_points` embeddings (B scaled with N; the oracle cannot
+    build the 1M x 4096 index in benchmark time, and its per-query cost is
+    dominated by the FP64 hashing, 4096 x L*K products, which does not
+    depend on N).  One core (the oracle's thread count set to 1), then all
+    host cores (one query per thread).  The mixed rate weighs the two
+    families' per-query times equally (the 50/50 mix)."""
     import numpy as np
     import oracle
     from workloads import configs
+    hi = host_info()
+    res, parts = {}, {}
+    g, r = ws
     t = time.time()
+    oracle.set_threads(hi["nproc"])
+    og = oracle.OracleIndex(oracle.MINHASH_U64, g.data, g.K, g.L, g.R, g.B, configs.INDEX_SEED,
+                            bucket_bits=g.b)
+    n_sub = min(relu_points, r.cfg["N"])
+    b_sub = max(1, int(round(r.B * n_sub / r.cfg["N"])))
+    orr = oracle.OracleIndex(oracle.SRP_BF16, r.data[:n_sub], r.K, r.L, r.R, b_sub,
+                             configs.INDEX_SEED)
+    log(f"oracle indexes built in {time.time() - t:.1f}s (not timed)")
+    agree = True
+    for th in (1, hi["nproc"]):
+        oracle.set_threads(th)
+        ng, tg, gi, gs = _oracle_time(og, g, seconds, 200 if th == 1 else 2000)
+        nr, tr, _, _ = _oracle_time(orr, r, seconds, 20 if th == 1 else 400)
+        agree &= bool(np.array_equal(gi, refs[0][0][:ng]) and np.array_equal(gs, refs[0][1][:ng]))
+        mixed = 2.0 / (tg / ng + tr / nr)
+        parts[th] = {"genome_qps": round(ng / tg, 2), "genome_queries": ng,
+                     "relu_qps": round(nr / tr, 2), "relu_queries": nr, "mixed_qps": round(mixed, 2)}
+        log(f"oracle on {th} thread(s): {parts[th]}")
+    oracle.set_threads(hi["nproc"])
+    one, allc = parts[1], parts[hi["nproc"]]
+    res = {"value": one["mixed_qps"], "unit": "queries/s", "cores": 1, "kind": "oracle",
+           "sample": (f"genome: first {one['genome_queries']} queries against the oracle's full "
+                      f"1M-read index; embeddings: first {one['relu_queries']} queries against an "
+                      f"oracle index of the first {n_sub} embeddings (B={b_sub}); hash + "
+                      "reverse-index counts + Algorithm 3 per query, index builds not timed; "
+                      "mixed = equal weight per family"),
+           "per_family_1core": one,
+           "all_cores": {"cores": hi["nproc"], **allc},
+           "host": hi, "gpu_matches_oracle_on_genome_sample": agree}
+    return res
+
+
+def cpu_baseline_single(w, ids, sc, seconds):
+    """The oracle on one core, then on all host cores, over the first
+    queries against its own full-size index (the genome and small dense
+    workloads; the others are subsampled as in the mixed baseline)."""
+    import numpy as np
+    import oracle
+    from workloads import configs
+    hi = host_info()
     ofam = {0: oracle.SRP_F32, 1: oracle.SRP_BF16, 2: oracle.MINHASH_U32,
             3: oracle.MINHASH_U64}[w.fam]
+    t = time.time()
+    oracle.set_threads(hi["nproc"])
     oi = oracle.OracleIndex(ofam, w.data, w.K, w.L, w.R, w.B, configs.INDEX_SEED,
                             bucket_bits=None if w.dense else w.b)
     log(f"oracle index built in {time.time() - t:.1f}s (not timed)")
-    done, agree = 0, True
-    t0 = time.perf_counter()
-    while done < w.nq and time.perf_counter() - t0 < seconds:
-        n = min(50, w.nq - done)
-        wi, ws = oi.query(w.host_slice(done, n), w.k, literal=True)
-        agree &= np.array_equal(wi, ids[done:done + n]) and np.array_equal(ws, sc[done:done + n])
-        done += n
-    cpu_s = time.perf_counter() - t0
-    log(f"oracle: {done} queries in {cpu_s:.1f}s -> {done / cpu_s:.2f} q/s; agree={agree}")
-    return {"value": round(done / cpu_s, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {w.nq} queries against the full-size oracle index "
-                      "(hash, reverse-index counts, literal Algorithm 3 walk; index build "
-                      "not timed)",
-            "gpu_matches_oracle_on_sample": bool(agree)}
+    out = {}
+    for th in (1, hi["nproc"]):
+        oracle.set_threads(th)
+        n, el, oi_ids, oi_sc = _oracle_time(oi, w, seconds, 100 if th == 1 else 2000)
+        out[th] = (n, el, bool(np.array_equal(oi_ids, ids[:n]) and np.array_equal(oi_sc, sc[:n])))
+        log(f"oracle on {th} thread(s): {n} queries in {el:.1f}s")
+    oracle.set_threads(hi["nproc"])
+    n, el, agree = out[1]
+    na, ela, _ = out[hi["nproc"]]
+    return {"value": round(n / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {w.nq} queries against the oracle's full-size index (hash, "
+                      "reverse-index counts, Algorithm 3; index build not timed)",
+            "all_cores": {"cores": hi["nproc"], "value": round(na / ela, 2), "queries": na},
+            "host": hi, "gpu_matches_oracle_on_sample": bool(agree)}
 
 
-METRIC = "queries/s at recall@10>=0.9, served vs plain batched; p50/p99 query latency"
-
+# ---------------------------------------------------------------------------
 
 def main():
     args = parse()
@@ -397,7 +655,6 @@ def main():
               "replicated per GPU with no exchange, so no multi-GPU figure is produced.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2106_11565_amd as fl
     from workloads import configs
@@ -412,79 +669,174 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {COPY_BYTES} bytes x 3")
         del src, dst
-    if args.workload == "c5":
-        return main_mixed(args, torch, fl, configs)
+    if args.mfma_error:
+        return main_mfma_error(args, torch, fl, configs)
     if args.pareto:
         return main_pareto(args, torch, fl, configs)
+    if args.workload == "c5":
+        return main_mixed(args, torch, fl, configs)
+    return main_single(args, torch, fl, configs)
 
+
+def main_mixed(args, torch, fl, configs):
+    ws = [Workload("c2", args.scale, torch, fl, configs, keep_data=True, tuned=not args.fixed),
+          Workload("c3", args.scale, torch, fl, configs, keep_data=True, tuned=not args.fixed)]
+    import numpy as np
+    # plain batched: each family's query set as one batch
+    plain_res, refs, st = [], [], []
+    for w in ws:
+        ms, ids, sc, out_d = plain(w, torch, args.steps, args.warmup, False)
+        refs.append((ids, sc))
+        s = stages(w, torch, fl, args.steps, False, out_d)
+        st.append(s)
+        plain_res.append({"workload": w.name, "K": w.K, "L": w.L, "nq": w.nq,
+                          "ms_per_step": round(ms, 4), "qps": round(w.nq / (ms / 1e3), 1),
+                          "stages_ms": {"hash": round(s["hash_ms"], 4),
+                                        "count_decode": round(s["decode_ms"], 4)}})
+        log(f"plain {w.name}: {w.nq / (ms / 1e3):,.0f} q/s")
+    nq_all = sum(w.nq for w in ws)
+    plain_ms = sum(r["ms_per_step"] for r in plain_res)
+    # the timed step: the mixed query set served from HBM
+    reqs = mixed_requests(ws, 4)
+    served = served_device_steps(fl, torch, ws, reqs, args.steps, args.warmup, refs)
+    log(f"served (device): {served}")
+    value = served["achieved_qps"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": served["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 (MinHash) | bf16 MFMA + f32 acc + f64 recheck (SRP)", "data": "synthetic",
+        "config": {"workload": "mixed serving: genome_reads_1M_minhash + relu_embed_1M_d4096_bf16",
+                   "step": f"{nq_all} queries ({ws[0].nq} genome reads + {ws[1].nq} embeddings) "
+                           f"served in {len(reqs)} requests of U{{1..512}} queries, families "
+                           "interleaved, inputs and results in HBM",
+                   "k": ws[0].k,
+                   "indexes": [{"workload": w.name, "N": w.cfg["N"], "K": w.K, "L": w.L, "R": w.R,
+                                "B": w.B, "bucket_bits": None if w.dense else w.b,
+                                "K_L": "tuned (fastest of the sweep with R1@10 >= 0.9)"
+                                if w.tuned else "as configured"} for w in ws],
+                   "server": {"max_inflight": 4, "max_batch": 4096, "mem_budget_GiB": 8}},
+        "served": served,
+        "plain": {"per_family": plain_res, "mixed_ms_per_step": round(plain_ms, 4),
+                  "mixed_qps": round(nq_all / (plain_ms / 1e3), 1)},
+    }
+    dom = max(st, key=lambda s: s["decode_ms"])
+    out["roofline"] = dom["query_roofline"]
+    out["rooflines"] = ([s["query_roofline"] for s in st] +
+                        [s["hash_roofline"] for s in st if "hash_roofline" in s] +
+                        [w.build_roofline() for w in ws])
+    if not args.no_recall:
+        out["recall"] = {w.name: recall(w, fl, r[0], args.recall_queries) for w, r in zip(ws, refs)}
+    if not args.no_serve:
+        out["served_host_inputs"] = served_host_burst(fl, ws, reqs, refs)
+        log(f"served (host): {out['served_host_inputs']}")
+        if not args.no_sweep:
+            rates = ([float(r) for r in args.rates.split(",")] if args.rates else
+                     [1e3, 3e3, 1e4, 3e4, 1e5, 2e5, 5e5, 1e6, 2e6])
+            out["served_poisson"] = poisson_sweep(fl, torch, ws, rates, refs)
+    for w in ws:
+        w.data_d = None
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_mixed(ws, refs, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def main_single(args, torch, fl, configs):
+    import numpy as np
     w = Workload(args.workload, args.scale, torch, fl, configs, keep_data=True,
                  tuned=not args.fixed)
     ms, ids, sc, out_d = plain(w, torch, args.steps, args.warmup, args.persistent)
     value = w.nq / (ms / 1e3)
     log(f"plain batched: {ms:.3f} ms/step -> {value:,.0f} q/s")
-    hash_ms, decode_ms, roof = stages(w, torch, fl, args.steps, args.persistent, out_d)
+    s = stages(w, torch, fl, args.steps, args.persistent, out_d)
     assert np.array_equal(out_d[0].cpu().numpy().view(np.uint32), ids), "decode-only != full path"
-
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": ("bf16+f32acc+f64" if w.fam == fl.SRP_BF16 else "f32+f64") if w.dense else "u64",
         "data": "synthetic",
-        "config": {"workload": w.cfg["name"], "N": w.cfg["N"], "nq": w.nq, "K": w.K, "L": w.L,
+        "config": {"workload": w.name, "N": w.cfg["N"], "nq": w.nq, "K": w.K, "L": w.L,
                    "R": w.R, "B": w.B, "bucket_bits": w.b, "k": w.k,
                    "persistent": bool(args.persistent),
-                   "K_L": "tuned (R1@10 >= 0.9 by over two standard errors on 3000 queries)"
-                   if w.tuned else "as configured"},
-        "build_s": round(w.build_s, 3),
+                   "K_L": "tuned (fastest of the sweep with R1@10 >= 0.9)" if w.tuned
+                   else "as configured"},
         "srp_rechecked_fraction": (round(w.index.info.srp_rechecked / (w.cfg["N"] * w.K * w.L), 6)
                                    if w.dense else None),
-        "stages_ms": {"hash": round(hash_ms, 4), "count_decode": round(decode_ms, 4)},
-        "roofline": roof,
+        "stages_ms": {"hash": round(s["hash_ms"], 4), "count_decode": round(s["decode_ms"], 4)},
+        "roofline": s["query_roofline"],
+        "rooflines": [s["query_roofline"]] + ([s["hash_roofline"]] if "hash_roofline" in s else [])
+                     + [w.build_roofline()],
     }
     if not args.no_recall:
         out["recall"] = recall(w, fl, ids, args.recall_queries)
-    if w.tuned:
-        # the configured (K, L), measured the same way on the same data
-        K0, L0 = w.cfg["K"], w.cfg["L"]
-        ix = fl.Index(w.data_d, w.fam, K0, L0, w.R, w.B, configs.INDEX_SEED,
-                      bucket_bits=0 if w.dense else w.b)
-        w2 = Workload.__new__(Workload)
-        w2.__dict__.update(w.__dict__)
-        w2.index, w2.K, w2.L = ix, K0, L0
-        ms0, ids0, _, _ = plain(w2, torch, args.steps, args.warmup, args.persistent)
-        fixed = {"K": K0, "L": L0, "qps": round(w.nq / (ms0 / 1e3), 1), "ms_per_step": round(ms0, 4)}
-        if not args.no_recall:
-            fixed["recall"] = recall(w2, fl, ids0, args.recall_queries)
-        out["configured_K_L"] = fixed
-        log(f"configured K={K0} L={L0}: {fixed}")
-        ix.close()
-    w.data_d = None
-
     if not args.no_serve:
         sizes = w.cfg.get("group_sizes")
-        burst = serve_run(fl, [w], sweep_requests(w, sizes), 0, 5, [(ids, sc)], args.persistent)
-        log(f"served burst: {burst}")
-        rates = [float(r) for r in args.rates.split(",")] if args.rates else [1e5, 1e6]
-        pois = []
-        for i, rate in enumerate(rates):
-            n_req = int(max(40, min(3000, rate * 1.0 / 256.5)))
-            rr = poisson_requests([w], n_req, 6 + i, sizes)
-            pois.append(serve_run(fl, [w], rr, rate, 7 + i, [(ids, sc)], args.persistent))
-            log(f"served Poisson @ {rate:,.0f} q/s: {pois[-1]}")
-        out["served"] = {"plain_qps": round(value, 1), "burst": burst, "poisson": pois}
-
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, ids, sc, args.cpu_seconds)
-
+        reqs = mixed_requests([w], 5, sizes)
+        out["served"] = served_device_steps(fl, torch, [w], reqs, max(1, args.steps // 4), 1,
+                                            [(ids, sc)])
+        out["served_host_inputs"] = served_host_burst(fl, [w], reqs, [(ids, sc)])
+        log(f"served: {out['served']} / host {out['served_host_inputs']}")
+    w.data_d = None
+    if not args.no_cpu and (w.cfg["N"] <= 1_000_000 and not (w.dense and w.cfg["d"] > 1024)):
+        out["cpu_baseline"] = cpu_baseline_single(w, ids, sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def main_mfma_error(args, torch, fl, configs):
+    """Accuracy of the bf16 matrix-core projections on the ReLU workload:
+    the fp32 value v32 of every projection of all queries and of a sample of
+    indexed rows, against the FP64 value v (host FP64 products of the stored
+    bf16 values), as |v32 - v| / (|x| |w|) beside the bound gamma the sign
+    certificate assumes; and whether any trusted sign is wrong."""
+    import numpy as np
+    import oracle
+    from workloads import configs as C
+    cfg, X, Q, _ = C.make("c3", scale=args.scale)
+    K, L = (cfg["K"], cfg["L"]) if args.fixed else (cfg["tuned"]["K"], cfg["tuned"]["L"])
+    idx = fl.Index(X[:4096], fl.SRP_BF16, K, L, 1, 1, C.INDEX_SEED)
+    w64 = oracle.hyperplanes(C.INDEX_SEED, K * L, cfg["d"])
+    wn = np.sqrt((w64 * w64).sum(axis=1))
+    w_d = torch.from_numpy(w64).cuda()
+    rng = np.random.default_rng(12)
+    n_rows = min(cfg["N"], 4000)
+    rows_idx = np.sort(rng.choice(cfg["N"], n_rows, replace=False))
+    res = []
+    for name, rows in (("queries", Q), ("indexed rows", X[rows_idx])):
+        worst, wrong, trusted_n, total, hist = 0.0, 0, 0, 0, np.zeros(8, dtype=np.int64)
+        for s in range(0, rows.shape[0], 1000):
+            part = rows[s:s + 1000]
+            proj, (gamma, tau_abs) = idx.debug_projections(part)
+            xd = torch.from_numpy(oracle.bf16_to_f64(part)).cuda()
+            v = (xd @ w_d.T).cpu().numpy()
+            xn = np.sqrt((oracle.bf16_to_f64(part) ** 2).sum(axis=1))
+            scale = xn[:, None] * wn[None, :]
+            ratio = np.abs(proj.astype(np.float64) - v) / np.maximum(scale, 1e-300)
+            worst = max(worst, float(ratio.max()))
+            # ratio / gamma in decades below the bound
+            dec = np.clip(np.floor(-np.log10(np.maximum(ratio / gamma, 1e-30))), 0, 7).astype(int)
+            hist += np.bincount(dec.ravel(), minlength=8)
+            tr = np.abs(proj) > gamma * scale + tau_abs
+            wrong += int(np.sum(np.sign(proj[tr]) != np.sign(v[tr])))
+            trusted_n += int(tr.sum())
+            total += proj.size
+        r = {"rows": name, "projections": total, "max_ratio": worst, "gamma": gamma,
+             "max_ratio_over_gamma": worst / gamma, "trusted": trusted_n,
+             "trusted_with_wrong_sign": wrong,
+             "ratio_over_gamma_decades": {f"1e-{i}..1e-{i + 1}" if i < 7 else "<1e-7": int(c)
+                                          for i, c in enumerate(hist)}}
+        log(r)
+        res.append(r)
+    print(json.dumps({"workload": cfg["name"], "K": K, "L": L, "d": cfg["d"], "results": res}),
+          flush=True)
 
 
 def truth_top1(w, fl, ns):
     """Exact nearest neighbour (lowest id on ties) of the first ns queries."""
     from workloads import truth
     if w.dense:
-        ti, _ = truth.cosine_topk_gpu(w.data, w.queries[:ns], 1, dense_bf16=(w.fam == fl.SRP_BF16))
+        ti, _ = truth.cosine_topk_gpu(w.data, w.queries[:ns], 1, dense_bf16=(w.fam == fl.SRP_BF16),
+                                      X_dev=w.data_d)
     else:
         ti, _ = truth.JaccardIndex(w.data[0], w.data[1]).topk(w.queries[0], w.queries[1][:ns + 1], 1)
     return ti[:, 0]
@@ -497,7 +849,8 @@ def main_pareto(args, torch, fl, configs):
     report the speed/recall frontier and the fastest setting with
     R1@10 >= 0.9.  For each K, L grows until two settings meet the target."""
     import numpy as np
-    w = Workload(args.workload, args.scale, torch, fl, configs, keep_data=True)
+    name = "c2" if args.workload == "c5" else args.workload
+    w = Workload(name, args.scale, torch, fl, configs, keep_data=True)
     ns = min(args.recall_queries, w.nq)
     t = time.time()
     top1 = truth_top1(w, fl, ns)
@@ -538,54 +891,15 @@ def main_pareto(args, torch, fl, configs):
     ok = [p for p in pts if p["R1@10"] >= 0.9]
     best = max(ok, key=lambda p: p["qps"]) if ok else None
     out = {"metric": METRIC, "value": best["qps"] if best else None, "unit": "queries/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": best["ms_per_step"] if best else None,
+           "n_gpus": 1, "steps": args.steps, "warmup": 2,
+           "ms_per_step": best["ms_per_step"] if best else None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u64" if not w.dense else "bf16+f32acc+f64", "data": "synthetic",
-           "config": {"workload": w.cfg["name"] + " (K, L) sweep", "N": w.cfg["N"], "nq": w.nq,
+           "config": {"workload": w.name + " (K, L) sweep", "N": w.cfg["N"], "nq": w.nq,
                       "R": w.R, "B": w.B, "bucket_bits": w.b, "k": w.k,
                       "fixed": {"K": w.K, "L": w.L}},
            "fastest_at_R1@10>=0.9": best, "frontier": sorted(front, key=lambda p: -p["qps"]),
            "points": pts, "recall_queries": ns}
-    print(json.dumps(out), flush=True)
-
-
-def main_mixed(args, torch, fl, configs):
-    """Genome reads (MinHash) and ReLU embeddings (SRP) resident together:
-    each family's plain batched rate, then a sweep of Poisson arrival rates of
-    mixed-family requests through one server, and a burst (saturation)."""
-    ws = [Workload("c2", args.scale, torch, fl, configs, tuned=not args.fixed),
-          Workload("c3", args.scale, torch, fl, configs)]
-    plain_res, refs = [], []
-    for w in ws:
-        ms, ids, sc, _ = plain(w, torch, args.steps, args.warmup, False)
-        plain_res.append({"workload": w.cfg["name"], "nq": w.nq, "ms_per_step": round(ms, 4),
-                          "qps": round(w.nq / (ms / 1e3), 1)})
-        refs.append((ids, sc))
-        log(f"plain {w.cfg['name']}: {w.nq / (ms / 1e3):,.0f} q/s")
-    # half the queries from each family, each family batched on its own
-    mixed_plain = sum(w.nq for w in ws) / sum(r["ms_per_step"] / 1e3 for r in plain_res)
-    rates = ([float(r) for r in args.rates.split(",")] if args.rates else
-             [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6, 2e6])
-    sweep = []
-    for i, rate in enumerate(rates):
-        n_req = int(max(30, min(3000, rate * 1.0 / 256.5)))
-        r = serve_run(fl, ws, poisson_requests(ws, n_req, 100 + i), rate, 200 + i, refs)
-        sweep.append(r)
-        log(f"served mixed Poisson @ {rate:,.0f} q/s: {r}")
-    burst = serve_run(fl, ws, poisson_requests(ws, 200, 99), 0, 98, refs)
-    log(f"served mixed burst: {burst}")
-    out = {
-        "metric": METRIC, "value": burst["achieved_qps"], "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64 | bf16+f32acc+f64", "data": "synthetic",
-        "config": {"workload": "mixed serving: genome_reads_1M_minhash + relu_embed_1M_d4096_bf16",
-                   "requests": "Poisson arrivals, sizes U{1..512}, family 50/50, k=10",
-                   "indexes": [{"workload": w.cfg["name"], "K": w.K, "L": w.L, "R": w.R, "B": w.B}
-                               for w in ws]},
-        "plain": plain_res, "plain_mixed_qps": round(mixed_plain, 1),
-        "served_poisson": sweep, "served_burst": burst,
-    }
     print(json.dumps(out), flush=True)
 
 

@@ -58,11 +58,21 @@ class JaccardIndex:
         return out_i, out_s
 
 
-def cosine_topk_gpu(X, Q, k, chunk=65536, dense_bf16=False):
+def cosine_topk_gpu(X, Q, k, chunk=65536, dense_bf16=False, X_dev=None):
     """Top-k ids by cosine similarity for large dense sets: candidates by a
     chunked fp32 scan on the GPU (torch), re-scored exactly in FP64 on the
-    host.  X, Q are host arrays (fp32, or bf16 bit patterns if dense_bf16)."""
+    host.  X, Q are host arrays (fp32, or bf16 bit patterns if dense_bf16);
+    X_dev, if given, is the same data already on the device (the scan then
+    reads it there)."""
     import torch
+
+    def dev_chunk(s):
+        if X_dev is None:
+            return torch.from_numpy(to_f32(X[s:s + chunk])).cuda()
+        c = X_dev[s:s + chunk]
+        if dense_bf16:
+            return ((c.to(torch.int32) & 0xFFFF) << 16).view(torch.float32)
+        return c.float()
 
     def to_f32(a):
         a = np.ascontiguousarray(a)
@@ -77,7 +87,7 @@ def cosine_topk_gpu(X, Q, k, chunk=65536, dense_bf16=False):
     best_s = torch.full((Qd.shape[0], 0), -2.0, device="cuda")
     best_i = torch.zeros((Qd.shape[0], 0), dtype=torch.int64, device="cuda")
     for s in range(0, X.shape[0], chunk):
-        Xc = torch.from_numpy(to_f32(X[s:s + chunk])).cuda()
+        Xc = dev_chunk(s)
         Xc = Xc / Xc.norm(dim=1, keepdim=True).clamp_min(1e-30)
         S = Qd @ Xc.T
         v, i = torch.topk(S, min(kk, S.shape[1]), dim=1)

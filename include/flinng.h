@@ -156,6 +156,32 @@ int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t 
                        uint32_t k, uint32_t *ids, uint32_t *scores,
                        uint32_t persistent, uint64_t *stats, void *stream);
 
+/*
+ * flinng_query_threshold -- Algorithm 2 (Index Query) at a fixed threshold:
+ * a cell's group test is positive when at least t of the L tables collide
+ * with the query (count >= t, the Section 3 filter rule), and a point is
+ * reported when its cell is positive in all R repetitions, i.e. the set
+ * {x : min_r C[r, g_r(x)] >= t}.  (flinng_query relaxes t per query instead,
+ * Algorithm 3; its output is this set at decreasing t.)
+ *  q        (host struct) nq = q->count queries of the index's family.
+ *  t        threshold, any value: 0 reports every point, t > L none.
+ *  max_per_query  id slots per query (may be 0: sizes only).
+ *  ids      (host or device per out_on_device) nq*max_per_query uint32,
+ *           row-major: each query's reported ids, as many as fit, unused
+ *           slots 0xFFFFFFFF.  They come grouped by the cells of one
+ *           repetition (ascending cell, then ascending id); compare them as
+ *           a set.  May be NULL when max_per_query is 0.
+ *  counts   (same placement) nq uint32: the size of each query's answer,
+ *           also when it exceeds max_per_query (query again with more slots
+ *           for the rest).
+ * Device outputs: returns once the work is enqueued; host outputs
+ * synchronize `stream`.  FLINNG_EINVAL for a bad input or when the B*R
+ * counters do not fit a workgroup's LDS.
+ */
+int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint32_t t,
+                           uint32_t max_per_query, uint32_t *ids, uint32_t *counts,
+                           uint32_t out_on_device, void *stream);
+
 /* Release an index and all its device memory (NULL is allowed). */
 void flinng_index_free(flinng_index *idx);
 
@@ -202,6 +228,47 @@ int flinng_debug_counts(const flinng_index *idx, const flinng_input *q,
  */
 int flinng_index_export(const flinng_index *idx, uint64_t *offsets,
                         uint32_t *cells, uint32_t *groups, void *stream);
+
+/* ---- parameters from the theory (Section 5 and its proofs) ------------- */
+/* Host arithmetic only (no device is touched).  Our notation: K hashes per
+ * table = the paper's L, L tables = the paper's m. */
+typedef struct flinng_theory {
+    uint32_t B;             /* groups per repetition, 2 sqrt(N) rounded        */
+    uint32_t R;             /* repetitions: the cellwise rate bound, rounded up */
+    uint32_t K;             /* hashes per table: smallest with
+                               s_k^K >= 2 (N/B) s_k1^K                           */
+    uint32_t L;             /* tables: smallest with alpha <= min(q, 1 - p)     */
+    uint32_t t;             /* threshold for flinng_query_threshold: ceil(t_real) */
+    uint32_t conditions_met;/* 1 when N >= 150 and R_real >= 10 ln N (the
+                               footnote of the bound)                           */
+    double R_real;          /* ln(1/delta) / (ln(4.80 sqrt N) -
+                               ln(2 e^2 + 3.44 sqrt N))                         */
+    double p, q;            /* test true / false positive rates required:
+                               p = 1 - delta / (2R), q = N^-1/2                 */
+    double one_minus_p;     /* delta / (2R), exact where p rounds to 1          */
+    double gamma;           /* the query's stability ln s_k / (ln s_k1 - ln s_k) */
+    double m_paper;         /* the closed form -8 ln(min(q, 1-p)) N^gamma       */
+    double t_real;          /* L * (t_over_m_low + t_over_m_high) / 2           */
+    double t_over_m_low;    /* (N/B) s_k1^K: negative groups' collision rate    */
+    double t_over_m_high;   /* s_k^K: positive groups' collision rate           */
+    double alpha;           /* filter error bound on either side at (K, L, t)   */
+} flinng_theory;
+
+/*
+ * flinng_theory_params -- the group-test design (B, R, and the rates p, q a
+ * test must reach; Lemma 1 and the cellwise rate bounds) and the
+ * distance-sensitive Bloom filter that reaches them (K, L, t; Theorem 1 with
+ * the threshold taken as t/m, the choices of t, B and L in the proof of the
+ * test-cost theorem) for N points, a query whose K-th and (K+1)-th nearest
+ * neighbours have per-hash collision probabilities s_k > s_k1, and failure
+ * probability delta.  L is computed for the integer K (the paper's closed
+ * form, which takes K real-valued, is returned as m_paper).
+ * FLINNG_EINVAL: N < 2, N <= 118 (the bound on R needs more points),
+ * similarities outside 0 < s_k1 < s_k < 1, delta outside (0, 1), or values
+ * out of range.
+ */
+int flinng_theory_params(uint64_t N, double s_k, double s_k1, double delta,
+                         flinng_theory *out);
 
 /* ---- serving: continuous batching over resident indexes ----------------- */
 typedef struct flinng_server flinng_server;

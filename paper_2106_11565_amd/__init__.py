@@ -11,9 +11,19 @@ import numpy as np
 
 from ._lib import (  # noqa: F401
     SRP_F32, SRP_BF16, MINHASH_U32, MINHASH_U64, FlinngError, Params, Input,
-    IndexInfo, ServeConfig, ServeStats, check, lib, make_input, current_stream,
+    IndexInfo, ServeConfig, ServeStats, Theory, check, lib, make_input, current_stream,
     EBUSY, EINVAL, ENOMEM, ETIMEDOUT, ESTATE,
 )
+
+
+def theory_params(N, s_k, s_k1, delta):
+    """flinng_theory_params: the design the paper's analysis gives for N
+    points, neighbour similarities s_k > s_k1 and failure probability delta
+    (B, R, K hashes per table, L tables, threshold t, and the rates)."""
+    th = Theory()
+    check(lib().flinng_theory_params(int(N), float(s_k), float(s_k1), float(delta),
+                                     ctypes.byref(th)))
+    return {f: getattr(th, f) for f, _ in Theory._fields_}
 
 
 def _stream(stream):
@@ -69,6 +79,17 @@ class Index:
                                  sc.ctypes.data, 0, int(persistent), _stream(stream)))
         del keep
         return ids, sc
+
+    def query_threshold(self, q, t, max_per_query, stream=None):
+        """flinng_query_threshold (Algorithm 2 at threshold t), host outputs:
+        (ids [nq, max_per_query] uint32 padded with 0xFFFFFFFF, counts [nq])."""
+        inp, keep = make_input(q, self.family)
+        nq = inp.count
+        ids = np.empty((nq, max(max_per_query, 1)), dtype=np.uint32)
+        cnt = np.empty(nq, dtype=np.uint32)
+        check(lib().flinng_query_threshold(self._h, ctypes.byref(inp), t, max_per_query,
+                                           ids.ctypes.data, cnt.ctypes.data, 0, _stream(stream)))
+        return ids[:, :max_per_query], cnt
 
     def debug_hash(self, q, stream=None):
         inp, keep = make_input(q, self.family)

@@ -57,6 +57,15 @@ class ServeStats(ctypes.Structure):
                 ("mean_batch", ctypes.c_double), ("peak_mem_bytes", c_u64)]
 
 
+class Theory(ctypes.Structure):
+    _fields_ = [("B", c_u32), ("R", c_u32), ("K", c_u32), ("L", c_u32), ("t", c_u32),
+                ("conditions_met", c_u32), ("R_real", ctypes.c_double), ("p", ctypes.c_double),
+                ("q", ctypes.c_double), ("one_minus_p", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("m_paper", ctypes.c_double),
+                ("t_real", ctypes.c_double), ("t_over_m_low", ctypes.c_double),
+                ("t_over_m_high", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -73,6 +82,10 @@ def lib():
             "flinng_build": (ctypes.c_int, [P(Params), P(Input), c_vp, P(c_vp)]),
             "flinng_query": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_u32, c_vp]),
             "flinng_query_codes": (ctypes.c_int, [c_vp, c_vp, c_u64, c_u32, c_vp, c_vp, c_u32, c_vp, c_vp]),
+            "flinng_query_threshold": (ctypes.c_int, [c_vp, P(Input), c_u32, c_u32, c_vp, c_vp, c_u32,
+                                                      c_vp]),
+            "flinng_theory_params": (ctypes.c_int, [c_u64, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, P(Theory)]),
             "flinng_index_free": (None, [c_vp]),
             "flinng_index_get_info": (ctypes.c_int, [c_vp, P(IndexInfo)]),
             "flinng_last_error": (ctypes.c_char_p, []),

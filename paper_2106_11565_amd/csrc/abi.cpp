@@ -286,6 +286,36 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uin
     });
 }
 
+int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint32_t t,
+                           uint32_t max_per_query, uint32_t *ids, uint32_t *counts,
+                           uint32_t out_on_device, void *stream) {
+    return guard([&] {
+        require(idx != nullptr, "index is NULL");
+        const Index &ix = *reinterpret_cast<const Index *>(idx);
+        validate_input(q, ix.p.family, "queries");
+        require(counts != nullptr, "counts is NULL");
+        require(ids != nullptr || max_per_query == 0, "ids is NULL");
+        const uint64_t nq = q->count;
+        if (nq == 0) return;
+        require(nq * (uint64_t)max_per_query <= (1ull << 40), "nq * max_per_query too large");
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf codes(nq * ix.p.L * 4, s);
+        hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        if (out_on_device) {
+            threshold_launch(ix, codes.as<uint32_t>(), nq, t, max_per_query, ids, counts, s);
+        } else {
+            DevBuf dids(nq * max_per_query * 4, s), dcnt(nq * 4, s);
+            threshold_launch(ix, codes.as<uint32_t>(), nq, t, max_per_query, dids.as<uint32_t>(),
+                             dcnt.as<uint32_t>(), s);
+            if (max_per_query)
+                FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * max_per_query * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipMemcpyAsync(counts, dcnt.ptr, nq * 4, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
 int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t nq, uint32_t k,
                        uint32_t *ids, uint32_t *scores, uint32_t persistent, uint64_t *stats,
                        void *stream) {

@@ -172,8 +172,9 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
 // The error bound the MFMA stage uses for a trusted sign: |v32 - v| <=
 // gamma * |x|_2 * |w|_2 + tau_abs (rounding of the norms included).
 void srp_bound(const Index &ix, double *gamma, double *tau_abs);
-// Upper bound of the scratch srp_hash takes for n rows already on the device.
-size_t srp_scratch_bytes(const Index &ix, uint64_t n);
+// Upper bound of the scratch srp_hash takes for n rows already on the device
+// (exact when the rows' device address xdev is given).
+size_t srp_scratch_bytes(const Index &ix, uint64_t n, const void *xdev = nullptr);
 void minhash_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
                   hipStream_t s, double mean_hint = -1.0);
 // mean_hint: mean items per set of a device-resident set batch (<= 0: unknown).
@@ -215,5 +216,10 @@ void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
                    uint8_t *counts_dev, hipStream_t s);
 size_t query_lds_bytes(const Index &ix, uint32_t k);
 uint32_t query_max_k();
+
+// Fixed-threshold query (threshold.hip): ids [nq][max_out] of the points with
+// m(x) >= t, counts [nq] the size of each answer.
+void threshold_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint32_t t,
+                      uint32_t max_out, uint32_t *ids_dev, uint32_t *counts_dev, hipStream_t s);
 
 }  // namespace flinng

@@ -670,10 +670,18 @@ void srp_bound(const Index &ix, double *gamma, double *tau_abs) {
     *tau_abs = (double)nsplit * ix.dpad * 0x1p-100;
 }
 
-size_t srp_scratch_bytes(const Index &ix, uint64_t n) {
+// bf16 rows are projected in place (no operand planes) when d is a multiple
+// of 32 and the rows start 16-byte aligned.
+static bool srp_inplace(const Index &ix, const void *xdev) {
+    return ix.p.family == FLINNG_SRP_BF16 && ix.p.dim == ix.dpad &&
+           (reinterpret_cast<uintptr_t>(xdev) & 15) == 0;
+}
+
+size_t srp_scratch_bytes(const Index &ix, uint64_t n, const void *xdev) {
     const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
     const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
-    return Arena::round((size_t)nsplit * n * ix.dpad * 2) + Arena::round(n * 4) +
+    const bool planes = !(xdev && srp_inplace(ix, xdev));
+    return (planes ? Arena::round((size_t)nsplit * n * ix.dpad * 2) : 0) + Arena::round(n * 4) +
            2 * Arena::round(n * Hw * 4) + Arena::round(16);
 }
 
@@ -697,7 +705,7 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         FL_HIP(hipMemcpyAsync(xcopy.ptr, in.values, n * d * esz, hipMemcpyHostToDevice, s));
         xdev = xcopy.ptr;
     }
-    const bool inplace = !f32 && (d == dpad) && ((reinterpret_cast<uintptr_t>(xdev) & 15) == 0);
+    const bool inplace = srp_inplace(ix, xdev);
     uint16_t *planes = sc.get<uint16_t>(inplace ? 0 : (size_t)nsplit * n * dpad * 2);
     float *nx = sc.get<float>(n * 4);
     uint32_t *bits = sc.get<uint32_t>(n * Hw * 4);

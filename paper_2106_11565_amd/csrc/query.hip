@@ -1265,6 +1265,10 @@ static void launch_q(const QArgs &a, size_t lds, bool persistent, hipStream_t s)
     }
 }
 
+__global__ void zero_u32_kernel(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
 static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint32_t k) {
     QArgs a{};
     a.codes = codes;
@@ -1306,7 +1310,12 @@ void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint3
     if ((int)lds > max_lds())
         fail(FLINNG_EINVAL, "per-query state (" + std::to_string(lds) +
                                 " bytes) exceeds the workgroup LDS limit; reduce B*R or k");
-    if (persistent) FL_HIP(hipMemsetAsync(work_counter, 0, 4, s));
+    // the persistent grid's query counter starts at 0 (cleared by a kernel,
+    // so that the launch can be captured into a graph)
+    if (persistent) {
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, work_counter);
+        FL_CHECK_LAUNCH();
+    }
     if (ix.cell_bytes == 2)
         launch_q<uint16_t>(a, lds, persistent, s);
     else

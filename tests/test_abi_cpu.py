@@ -42,18 +42,28 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.Input) == 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(L.ServeConfig) == 8 + 4 * 4 + 8
     hdr = open(HEADER).read()
-    for struct, cls in (("flinng_params", L.Params), ("flinng_input", L.Input)):
+    for struct, cls in (("flinng_params", L.Params), ("flinng_input", L.Input),
+                        ("flinng_index_info", L.IndexInfo), ("flinng_serve_config", L.ServeConfig),
+                        ("flinng_serve_stats", L.ServeStats), ("flinng_theory", L.Theory)):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct, struct), hdr, re.S).group(1)
-        fields = re.findall(r"\b([A-Za-z_]+);", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            # "type a, b, c" -> a, b, c
+            first, *rest = [x.strip() for x in decl.split(",")]
+            fields.append(first.split()[-1].lstrip("*"))
+            fields += [r.lstrip("*") for r in rest]
         assert fields == [f for f, _ in cls._fields_], (struct, fields)
 
 
 def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
-    """The binding refuses to run without the HIP library."""
-    import importlib
+    """The binding refuses to run without the HIP library (monkeypatch puts
+    the module's state back afterwards)."""
     import paper_2106_11565_amd._lib as L
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(ImportError):
         L.lib()
-    importlib.reload(L)

@@ -258,6 +258,51 @@ def test_errors(fl):
         gi.query(X[:3], 0)
     with pytest.raises(fl.FlinngError):
         gi.query(X[:3], 5000)
+    # on_device = 2 (device items, host offsets) is a serving-only placement
+    import ctypes
+    inp, keep = fl.make_input(X[:3], 0)
+    inp.on_device = 2
+    ids = np.empty((3, 5), dtype=np.uint32)
+    rc = fl.lib().flinng_query(gi.handle, ctypes.byref(inp), 5, ids.ctypes.data, None, 0, 0, None)
+    assert rc == fl.EINVAL
+    # the theory helper and the projections export reject what they cannot do
+    with pytest.raises(fl.FlinngError):
+        fl.theory_params(100, 0.9, 0.5, 0.1)
+    it, of, qit, qof, _ = synth.genome(n_base=60, nq=4)
+    si = fl.Index((it, of), fl.MINHASH_U64, 1, 4, 2, 5, seed=1, bucket_bits=10)
+    with pytest.raises(fl.FlinngError):
+        si.debug_projections((qit, qof))
+
+
+@pytest.mark.parametrize("name,scale,nq,fam", [("c1", 1.0, 100, 0), ("c2", 0.01, 80, 3),
+                                                ("c3", 0.006, 40, 1), ("c4", 0.002, 80, 2)])
+def test_fixed_threshold_equals_oracle(fl, name, scale, nq, fam):
+    """flinng_query_threshold (Algorithm 2 at a fixed t) returns exactly the
+    oracle's {x : every repetition's cell of x has count >= t}, for t from 0
+    (every point) to L + 1 (none); the counts are exact even when fewer id
+    slots are given, and the truncated ids are a prefix of the full answer."""
+    cfg, data, q, _ = scaled(name, scale, nq)
+    bb = {0: 0, 1: 0, 3: cfg["bucket_bits"], 2: 18}[fam]
+    gi, oi = build_both(fl, fam, data, cfg["K"], cfg["L"], cfg["R"], cfg["B"], 31, bb)
+    cnt = oi.counts(oi.hash(q))
+    L = cfg["L"]
+    for t in sorted({0, 1, 2, max(1, L // 2), L - 1, L, L + 1}):
+        want = [np.nonzero(oracle.query_fixed_t(cnt[i], oi.g, oi.B, t))[0] for i in range(nq)]
+        M = max(1, max(len(w) for w in want))
+        ids, counts = gi.query_threshold(q, t, M)
+        log("threshold", name, "t", t, "largest answer", M)
+        for i in range(nq):
+            assert counts[i] == len(want[i]), (t, i)
+            assert np.array_equal(np.sort(ids[i][:counts[i]]), want[i]), (t, i)
+            assert np.all(ids[i][counts[i]:] == 0xFFFFFFFF)
+        small = max(1, M // 3)
+        ids2, counts2 = gi.query_threshold(q, t, small)
+        assert np.array_equal(counts2, counts)
+        for i in range(nq):
+            n = min(small, int(counts[i]))
+            assert np.array_equal(ids2[i][:n], ids[i][:n]), (t, i)
+        _, counts0 = gi.query_threshold(q, t, 0)
+        assert np.array_equal(counts0, counts)
 
 
 def test_c4_grid_u32_cells_large_lds(fl):

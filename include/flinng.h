@@ -182,6 +182,28 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
                            uint32_t max_per_query, uint32_t *ids, uint32_t *counts,
                            uint32_t out_on_device, void *stream);
 
+/*
+ * flinng_query_noalloc -- flinng_query for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but every piece of scratch
+ * (the batch's bucket codes, the SRP stage's norms, sign/flag words and
+ * counters, the persistent grid's counter) comes from one 64 MiB device
+ * array that the library holds per GPU until the process ends; nothing is
+ * allocated or freed, and nothing is cleared with a memset call.
+ *  q        device input only (q->on_device = 1), as in flinng_query.
+ *  ids, scores  device outputs, nq*k uint32 as in flinng_query (scores may
+ *           be NULL).
+ * Returns once the work is enqueued on `stream`.  FLINNG_EINVAL when the
+ * batch needs more scratch than the array holds (about nq*L*4 bytes plus,
+ * for dense indexes, nq*(4 + 8*ceil(K*L/32)) bytes and, unless bf16 rows
+ * with dim a multiple of 32 are used in place, the bf16 operand planes of
+ * nq*dim*2 bytes, three for fp32 rows): split the batch.  Calls that
+ * overlap on one GPU share the array and race: serialize them (one stream,
+ * or events).
+ */
+int flinng_query_noalloc(const flinng_index *idx, const flinng_input *q, uint32_t k,
+                         uint32_t *ids, uint32_t *scores, uint32_t persistent, void *stream);
+
 /* Release an index and all its device memory (NULL is allowed). */
 void flinng_index_free(flinng_index *idx);
 

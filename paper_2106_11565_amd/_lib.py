@@ -82,6 +82,7 @@ def lib():
             "flinng_build": (ctypes.c_int, [P(Params), P(Input), c_vp, P(c_vp)]),
             "flinng_query": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_u32, c_vp]),
             "flinng_query_codes": (ctypes.c_int, [c_vp, c_vp, c_u64, c_u32, c_vp, c_vp, c_u32, c_vp, c_vp]),
+            "flinng_query_noalloc": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_vp]),
             "flinng_query_threshold": (ctypes.c_int, [c_vp, P(Input), c_u32, c_u32, c_vp, c_vp, c_u32,
                                                       c_vp]),
             "flinng_theory_params": (ctypes.c_int, [c_u64, ctypes.c_double, ctypes.c_double,

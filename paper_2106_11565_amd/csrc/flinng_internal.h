@@ -217,6 +217,9 @@ void counts_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,
 size_t query_lds_bytes(const Index &ix, uint32_t k);
 uint32_t query_max_k();
 
+// Scratch bytes flinng_query_noalloc carves for nq queries (noalloc.hip).
+size_t noalloc_scratch_bytes(const Index &ix, uint64_t nq, const void *xdev);
+
 // Fixed-threshold query (threshold.hip): ids [nq][max_out] of the points with
 // m(x) >= t, counts [nq] the size of each answer.
 void threshold_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, uint32_t t,

@@ -130,9 +130,9 @@ int flinng_build(const flinng_params *p, const flinng_input *data,
  *  persistent  0: one workgroup per query; 1: a persistent grid that pulls
  *           queries from a device counter (for uneven batches in one launch).
  * Device outputs: the call returns once the work is enqueued on `stream`.
- * Host outputs: the call synchronizes `stream`.  The index data is
- * read-only, so concurrent calls (from any threads, on any streams) are
- * allowed.  The batch's codes go to a device region the index keeps for
+ * Host outputs: the call synchronizes `stream`.  Queries only read the index,
+ * so concurrent calls (from any threads, on any streams) are allowed, also
+ * beside flinng_index_insert (each call sees one version of the index).  The batch's codes go to a device region the index keeps for
  * each stream it is queried on (up to 8 streams; allocated on first use,
  * grown synchronously for a larger batch, freed by flinng_index_free).
  */
@@ -203,6 +203,28 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
  */
 int flinng_query_noalloc(const flinng_index *idx, const flinng_input *q, uint32_t k,
                          uint32_t *ids, uint32_t *scores, uint32_t persistent, void *stream);
+
+/*
+ * flinng_index_insert -- add points to a built, resident index (the index is
+ * built in one pass over the data, so later points join the same way).
+ *  data   (host struct) data->count points of the index's family, host or
+ *         device per data->on_device (0 or 1); borrowed for the call.  They
+ *         get ids N, N+1, ... in order (N = the index's size before).
+ * Each point is hashed with the index's functions and joins one group per
+ * repetition.  Algorithm 1's permutation is drawn for the N0 points of the
+ * build, so the arrivals follow their own rule: in arrival order they form
+ * blocks of B, and block j places its u-th point in group pi_{r,j}(u), a
+ * keyed random permutation of the B groups of repetition r.  Every complete
+ * block adds one point to each group, so group sizes stay within two of
+ * each other.  The point's cell then enters the reverse-index list of its
+ * bucket in every table (lists stay deduplicated sets, members ascending).
+ * New arrays are built beside the old ones (the index's memory transiently
+ * doubles) and swapped in while no query is being enqueued: queries and
+ * served batches in flight or queued see the index either before or after
+ * the insert, never a mix.  The call synchronizes the device.  One insert
+ * runs at a time per index; FLINNG_EINVAL past 2^32 - 2 points.
+ */
+int flinng_index_insert(flinng_index *idx, const flinng_input *data, void *stream);
 
 /* Release an index and all its device memory (NULL is allowed). */
 void flinng_index_free(flinng_index *idx);

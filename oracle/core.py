@@ -51,6 +51,7 @@ def _bind(L):
         "or_permute": (u64, [u64, u32, u64, u64]),
         "or_groups": (None, [u64, u32, u32, u64, vp]),
         "or_members": (None, [vp, u64, u32, u32, vp, vp]),
+        "or_stream_groups": (None, [u64, u32, u32, u64, u64, u64, vp]),
         "or_build_lists": (i64, [vp, vp, u64, u32, u32, u32, u32, vp, vp, u64]),
         "or_counts": (None, [vp, vp, u32, u32, u32, vp, u64, vp]),
         "or_counts_brute": (None, [vp, vp, u64, u32, u32, u32, vp, u64, vp]),
@@ -134,6 +135,15 @@ def groups(N, R, B, seed):
     """g[r, x] = P_r(x) mod B (Algorithm 1)."""
     g = np.empty((R, N), dtype=np.uint32)
     lib().or_groups(N, R, B, seed, _p(g))
+    return g
+
+
+def stream_groups(N0, R, B, seed, x0, n):
+    """Groups (R x n) of the points x0 .. x0+n-1 that arrive after the first
+    N0: blocks of B arrivals, each a keyed permutation of the B groups."""
+    g = np.empty((R, n), dtype=np.uint32)
+    if n:
+        lib().or_stream_groups(N0, R, B, seed, x0, n, _p(g))
     return g
 
 
@@ -239,7 +249,20 @@ class OracleIndex:
             self.N = len(offs) - 1
             self.codes = minhash_codes(items, offs, seed, K, L, bucket_bits)
         self.g = groups(self.N, R, B, seed)
+        self.N0 = self.N
         self.offsets, self.cells = build_lists(self.codes, self.g, B, self.nbits)
+
+    def insert(self, data):
+        """Points arriving after the build (ids N, N+1, ...): hashed with the
+        same functions, grouped by stream_groups, and the reverse index
+        rebuilt over all points."""
+        codes = self.hash(data)
+        n = codes.shape[0]
+        g = stream_groups(self.N0, self.R, self.B, self.seed, self.N, n)
+        self.codes = np.concatenate([self.codes, codes])
+        self.g = np.concatenate([self.g, g], axis=1)
+        self.N += n
+        self.offsets, self.cells = build_lists(self.codes, self.g, self.B, self.nbits)
 
     def _dense(self, data):
         if self.family == SRP_BF16:

@@ -230,6 +230,38 @@ void or_groups(uint64_t N, uint32_t R, uint32_t B, uint64_t seed, uint32_t *g)
     }
 }
 
+/* Groups of points that arrive after the index was built (reading: the
+ * paper builds its index in one pass over the data, and Algorithm 1 needs
+ * the final N for its permutation).  The arrivals after the first N0 points
+ * are cut into blocks of B in arrival order; within block j the point at
+ * position u joins group pi_{r,j}(u) of repetition r, where pi_{r,j} is a
+ * 4-round balanced Feistel network on [0, 2^nb) (nb the smallest even width
+ * >= 2 with 2^nb >= B) restricted to [0, B) by cycle walking, round keys
+ * sm64(key_STREAM, 4 (16 j + r) + i).  Every complete block adds exactly one
+ * point to each group of each repetition, so the group sizes stay within
+ * two of each other; the repetitions use independent permutations.
+ * g: R x n, repetition-major, for the points x0 .. x0+n-1 (x0 >= N0).     */
+enum { OR_TAG_STREAM = 4 };
+
+void or_stream_groups(uint64_t N0, uint32_t R, uint32_t B, uint64_t seed,
+                      uint64_t x0, uint64_t n, uint32_t *g)
+{
+    const uint64_t key = or_stream(seed, OR_TAG_STREAM);
+    const uint32_t half = or_feistel_bits(B) / 2;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t a = x0 + i - N0;
+        const uint64_t j = a / B, u = a % B;
+        for (uint32_t r = 0; r < R; ++r) {
+            uint64_t keys[4];
+            for (int k = 0; k < 4; ++k)
+                keys[k] = or_sm64(key, 4 * (16 * j + r) + (uint64_t)k);
+            uint64_t y = or_feistel(u, half, keys);
+            while (y >= B) y = or_feistel(y, half, keys);
+            g[(uint64_t)r * n + i] = (uint32_t)y;
+        }
+    }
+}
+
 /* Members of every cell (r, b), ascending point id (reading: within a cell the
  * relaxation walks points in ascending id).  mem_off: R*(B+1), mem: R*N.     */
 void or_members(const uint32_t *g, uint64_t N, uint32_t R, uint32_t B,

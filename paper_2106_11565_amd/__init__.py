@@ -50,11 +50,20 @@ class Index:
                                  ctypes.byref(h)))
         self._h = h
         del keep
-        self.info = self.get_info()
 
     @property
     def handle(self):
         return self._h
+
+    @property
+    def info(self):
+        return self.get_info()
+
+    def insert(self, data, stream=None):
+        """flinng_index_insert: add points (ids N, N+1, ...) to the index."""
+        inp, keep = make_input(data, self.family)
+        check(lib().flinng_index_insert(self._h, ctypes.byref(inp), _stream(stream)))
+        del keep
 
     def get_info(self):
         info = IndexInfo()

@@ -88,6 +88,7 @@ def lib():
             "flinng_theory_params": (ctypes.c_int, [c_u64, ctypes.c_double, ctypes.c_double,
                                                     ctypes.c_double, P(Theory)]),
             "flinng_index_free": (None, [c_vp]),
+            "flinng_index_insert": (ctypes.c_int, [c_vp, P(Input), c_vp]),
             "flinng_index_get_info": (ctypes.c_int, [c_vp, P(IndexInfo)]),
             "flinng_last_error": (ctypes.c_char_p, []),
             "flinng_debug_hash": (ctypes.c_int, [c_vp, P(Input), c_vp, c_u32, c_vp]),

@@ -114,6 +114,7 @@ static void free_index(Index *ix) {
     if (ix->cmg) (void)hipFree(ix->cmg);
     if (ix->hyp) (void)hipFree(ix->hyp);
     if (ix->hypnorm) (void)hipFree(ix->hypnorm);
+    if (ix->gsize) (void)hipFree(ix->gsize);
     delete ix;
 }
 
@@ -160,10 +161,12 @@ int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
             while (ix->Rp < p->R) ix->Rp <<= 1;
             const uint32_t Bp = (p->B + 3) & ~3u;
             ix->cell_bytes = ((uint64_t)p->R * Bp <= 65536) ? 2 : 4;
-            const uint64_t N = ix->N, nbk = nbuckets(*ix);
+            const uint64_t N = ix->N;
             uint64_t bytes = 0;
-            ix->offsets = dmalloc<uint32_t>((uint64_t)p->L * (nbk + 1), bytes);
+            ix->N0 = N;
+            ix->grp_cap = N;
             ix->grp = dmalloc<uint16_t>(N * ix->Rp, bytes);
+            ix->gsize = dmalloc<uint32_t>((uint64_t)p->R * p->B, bytes);
             const uint64_t gmax = (N + p->B - 1) / p->B;
             ix->mstride = (uint32_t)((gmax + 3) & ~3ull);
             ix->mem = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
@@ -188,8 +191,7 @@ int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
             build_groups(*ix, s);
             build_lists(*ix, codes.as<uint32_t>(), s);
             FL_HIP(hipStreamSynchronize(s));
-            bytes += cells_alloc_bytes(ix->list_entries, ix->cell_bytes);
-            ix->device_bytes = bytes;
+            ix->device_bytes = index_device_bytes(*ix);
         } catch (...) {
             free_index(ix);
             throw;
@@ -200,10 +202,42 @@ int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
 
 void flinng_index_free(flinng_index *idx) { free_index(reinterpret_cast<Index *>(idx)); }
 
+int flinng_index_insert(flinng_index *idx, const flinng_input *data, void *stream) {
+    return guard([&] {
+        require(idx != nullptr, "index is NULL");
+        Index &ix = *reinterpret_cast<Index *>(idx);
+        validate_input(data, ix.p.family, "data");
+        const uint64_t n = data->count;
+        if (n == 0) return;
+        FL_HIP(hipSetDevice(ix.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::lock_guard<std::mutex> one(ix.insert_mu);
+        require(ix.N + n <= 0xFFFFFFFEull, "at most 2^32-2 points");
+        const bool dense = is_dense(ix.p.family);
+        DevBuf codes(n * ix.p.L * 4, s);
+        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix.dpad * 16))
+                                     : (1ull << 20);
+        uint64_t rechecked = 0, exact = 0;
+        for (uint64_t b0 = 0; b0 < n; b0 += chunk) {
+            const uint64_t m = std::min(chunk, n - b0);
+            flinng_input part = slice(*data, ix, b0, m);
+            uint64_t ctr[2] = {0, 0};
+            hash_batch(ix, part, codes.as<uint32_t>() + b0 * ix.p.L, s, dense ? ctr : nullptr);
+            rechecked += ctr[0];
+            exact += ctr[1];
+        }
+        insert_points(ix, codes.as<uint32_t>(), n, s);
+        std::unique_lock<std::shared_mutex> lk(ix.rw);
+        ix.srp_rechecked += rechecked;
+        ix.srp_exact += exact;
+    });
+}
+
 int flinng_index_get_info(const flinng_index *idx, flinng_index_info *info) {
     return guard([&] {
         require(idx && info, "NULL argument");
         const Index &ix = *reinterpret_cast<const Index *>(idx);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
         std::memset(info, 0, sizeof(*info));
         info->N = ix.N;
         info->list_entries = ix.list_entries;
@@ -267,6 +301,7 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uin
         if (nq == 0) return;
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);  // one index version per call
         std::unique_lock<std::mutex> lock(ix.scratch_mu);
         uint32_t *codes = codes_scratch(ix, s, (size_t)nq * ix.p.L * 4);
         hash_batch(ix, *q, codes, s, nullptr);
@@ -274,11 +309,13 @@ int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uin
         if (out_on_device) {
             query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>());
             lock.unlock();
+            rl.unlock();
         } else {
             DevBuf dids(nq * k * 4, s), dsc(scores ? nq * k * 4 : 0, s);
             query_launch(ix, codes, nq, k, dids.as<uint32_t>(), scores ? dsc.as<uint32_t>() : nullptr,
                          persistent != 0, s, work.as<uint32_t>());
             lock.unlock();
+            rl.unlock();
             FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
             if (scores) FL_HIP(hipMemcpyAsync(scores, dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
             FL_HIP(hipStreamSynchronize(s));
@@ -302,6 +339,7 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
         hipStream_t s = static_cast<hipStream_t>(stream);
         DevBuf codes(nq * ix.p.L * 4, s);
         hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
         if (out_on_device) {
             threshold_launch(ix, codes.as<uint32_t>(), nq, t, max_per_query, ids, counts, s);
         } else {
@@ -327,6 +365,7 @@ int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t 
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
         DevBuf work(persistent ? 4 : 0, s);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
         query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>(),
                      reinterpret_cast<unsigned long long *>(stats));
     });
@@ -392,6 +431,7 @@ int flinng_debug_counts(const flinng_index *idx, const flinng_input *q, uint8_t 
         const uint64_t nc = (uint64_t)ix.p.R * ix.p.B;
         DevBuf codes(nq * ix.p.L * 4, s);
         hash_batch(ix, *q, codes.as<uint32_t>(), s, nullptr);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
         if (out_on_device) {
             counts_launch(ix, codes.as<uint32_t>(), nq, counts, s);
         } else {
@@ -410,6 +450,7 @@ int flinng_index_export(const flinng_index *idx, uint64_t *offsets, uint32_t *ce
         const Index &ix = *reinterpret_cast<const Index *>(idx);
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
         const uint64_t nbk = nbuckets(ix);
         const uint32_t B = ix.p.B, Bp = (B + 3) & ~3u;
         if (offsets) {

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -37,7 +38,7 @@ void set_last_error(const std::string &msg);
 // SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014) applied to
 // state s + (i+1) * 0x9E3779B97F4A7C15, i.e. the i-th output of a SplitMix64
 // stream started at s.  Stream keys: sm64(seed, tag).
-enum : uint64_t { TAG_HYP = 1, TAG_MINHASH = 2, TAG_GROUP = 3 };
+enum : uint64_t { TAG_HYP = 1, TAG_MINHASH = 2, TAG_GROUP = 3, TAG_STREAM = 4 };
 
 __host__ __device__ inline uint64_t splitmix_finalize(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -62,11 +63,18 @@ __host__ __device__ inline uint64_t sm64(uint64_t s, uint64_t i) {
 //   cmg       [R][B][mstride][Rp] uint16 cell-major copy of the groups: the
 //             row of the member in each slot of mem, so a decode pass reads
 //             every candidate's R groups sequentially beside its id
+//   gsize     [R][B]          uint32 members of each cell
 //   hyp       [L*K][dpad]     bf16 hyperplanes (dense families)
 //   hypnorm   [L*K]           fp32 Euclidean norms of the hyperplanes
+// Points inserted after the build (ids N0, N0+1, ...) are added by building
+// new offsets/cells/mem/cmg/gsize arrays beside the old ones and swapping
+// them in under `rw` (exclusive), so a query enqueued under `rw` (shared)
+// sees one version; the old arrays are freed once the device is idle.
 struct Index {
     flinng_params p{};
     uint64_t N = 0;
+    uint64_t N0 = 0;             // points of the one-pass build
+    uint64_t grp_cap = 0;        // point rows allocated in grp
     uint32_t nbits = 0;          // bucket width (K for SRP)
     uint32_t dpad = 0;           // dense: dim rounded up to 32
     uint32_t Rp = 1;
@@ -83,6 +91,12 @@ struct Index {
     uint16_t *cmg = nullptr;
     uint16_t *hyp = nullptr;
     float *hypnorm = nullptr;
+    uint32_t *gsize = nullptr;
+    uint32_t gmax = 0;                    // the largest cell
+    std::vector<uint32_t> gsize_host;     // host copy of gsize
+    std::vector<uint64_t> tstart;         // [L+1] first list entry of each table
+    mutable std::shared_mutex rw;         // query enqueue (shared) / insert swap
+    std::mutex insert_mu;                 // one insert at a time
     // Device scratch for the codes of one query batch, one region per
     // stream the index is queried on: work on one stream runs in order, so
     // a region is reused without waiting.  Grown (and evicted) with a
@@ -104,6 +118,15 @@ inline size_t cells_alloc_bytes(uint64_t n, size_t csz) {
     return ((n * csz + 15) & ~(size_t)15) + 16;
 }
 inline bool is_dense(uint32_t fam) { return fam == FLINNG_SRP_F32 || fam == FLINNG_SRP_BF16; }
+// Device bytes an index holds (all its arrays).
+inline uint64_t index_device_bytes(const Index &ix) {
+    const uint64_t ncells = (uint64_t)ix.p.R * ix.p.B;
+    uint64_t b = (uint64_t)ix.p.L * (nbuckets(ix) + 1) * 4 +
+                 cells_alloc_bytes(ix.list_entries, ix.cell_bytes) + ix.grp_cap * ix.Rp * 2 +
+                 ncells * ix.mstride * (4 + 2ull * ix.Rp) + ncells * 4;
+    if (is_dense(ix.p.family)) b += (uint64_t)ix.p.L * ix.p.K * (ix.dpad * 2 + 4);
+    return b;
+}
 
 // Device scratch allocated on a stream (stream-ordered allocator).
 struct DevBuf {
@@ -206,6 +229,10 @@ void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals,
 // Build pieces (build.hip).
 void build_groups(Index &ix, hipStream_t s);
 void build_lists(Index &ix, const uint32_t *codes_dev, hipStream_t s);
+// Add n points (ids ix.N ..) whose codes [n][L] are on the device: groups by
+// the arrival rule, members, reverse index; swaps the new arrays in.  The
+// caller holds ix.insert_mu.  Synchronizes the device.
+void insert_points(Index &ix, const uint32_t *codes_dev, uint64_t n, hipStream_t s);
 
 // Query (query.hip).
 void query_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq,

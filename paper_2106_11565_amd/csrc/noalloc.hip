@@ -92,6 +92,7 @@ extern "C" int flinng_query_noalloc(const flinng_index *idx, const flinng_input 
                                     " the allocation-free query holds; split the batch");
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
+        std::shared_lock<std::shared_mutex> rl(ix.rw);  // one index version per call
         Arena ws{device_scratch(), NOALLOC_SCRATCH_BYTES, 0};
         uint32_t *codes = static_cast<uint32_t *>(ws.take(nq * (size_t)ix.p.L * 4));
         uint32_t *work = static_cast<uint32_t *>(ws.take(4));

@@ -59,7 +59,8 @@ struct QArgs {
     const uint32_t *mem;   // [R][B][mstride] member ids
     const uint16_t *cmg;   // [R][B][mstride][Rp] member group rows
     uint64_t N;
-    uint32_t q0, rem;      // group sizes: N / B, and the groups b < N % B hold one more
+    const uint32_t *gsize; // [R][B] members of each cell
+    uint32_t gmax;         // the largest cell
     uint32_t L, R, Rp, B, Bp, nbits, k, cap;
     uint32_t mstride;      // member slots per cell (multiple of 4)
     uint32_t threads;      // workgroup size the kernel is launched with
@@ -386,7 +387,7 @@ template <int RP, int U, int T>
 __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32_t *__restrict__ memr,
                                   const uint16_t *__restrict__ cmgr, const uint8_t *cnt8, uint32_t R,
                                   uint32_t Bp, uint32_t mstride, uint32_t level, bool keep,
-                                  uint32_t q0, uint32_t rem, uint32_t cpc, uint32_t k, int lane,
+                                  const uint32_t *__restrict__ gsz, uint32_t cpc, uint32_t k, int lane,
                                   int wave, WaveState &ws) {
     constexpr int TW = T / 64;
     const uint32_t nitems = nl * cpc;
@@ -403,7 +404,7 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
             const uint32_t ci = cpc == 1 ? ic : ic / cpc;
             const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
             const uint32_t j0 = (ic - ci * cpc) * 256;
-            const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
+            const uint32_t sz = gsz[bb];
             const uint32_t j = j0 + 4 * lane;
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
             if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
@@ -522,8 +523,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint32_t L = A.L, R = A.R, B = A.B, Bp = A.Bp, k = A.k, cap = A.cap;
     const uint64_t nbk1 = (1ull << A.nbits) + 1;
-    const uint32_t q0 = A.q0, rem = A.rem;
-    const uint32_t gmax = q0 + (rem ? 1u : 0u);
+    const uint32_t gmax = A.gmax;
     const uint32_t cpc = (gmax + 255) / 256;  // 256-member chunks per cell
     const uint64_t rstride = (uint64_t)B * A.mstride;
     const CellT *cells = static_cast<const CellT *>(A.cells);
@@ -876,8 +876,8 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     }
                 }
                 __syncthreads();
-                walk_cells<RP, WU, QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep, q0,
-                                       rem, cpc, k, lane, wave, ws);
+                walk_cells<RP, WU, QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
+                                       A.gsize + rep * B, cpc, k, lane, wave, ws);
             } else {
                 const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
                 for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
@@ -892,7 +892,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     const uint32_t nl = misc[M_LCNT];
                     if (nl > CL - QT || cb0 + QT >= B) {
                         walk_cells<RP, WU, QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
-                                               q0, rem, cpc, k, lane, wave, ws);
+                                               A.gsize + rep * B, cpc, k, lane, wave, ws);
                         __syncthreads();
                         if (tid == 0) misc[M_LCNT] = 0;
                         __syncthreads();
@@ -948,7 +948,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 uint32_t cval = 0;
                 if (b < B) cval = 255u - cnt8[rep * Bp + b];
                 const bool pos = (b < B) && (cval >= level);
-                const uint32_t sz = pos ? (q0 + (b < rem ? 1u : 0u)) : 0u;
+                const uint32_t sz = pos ? A.gsize[rep * B + b] : 0u;
                 uint32_t npos, tsz;
                 const uint32_t ci = wg_excl_scan<QT>(pos ? 1u : 0u, scr, &npos);
                 const uint32_t ps = wg_excl_scan<QT>(sz, scr, &tsz);
@@ -1051,7 +1051,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                         while (zm && need) {
                             const uint32_t bb = b0 + (uint32_t)(__ffsll((long long)zm) - 1);
                             zm &= zm - 1;
-                            const uint32_t sz = q0 + (bb < rem ? 1u : 0u);
+                            const uint32_t sz = A.gsize[(R - 1) * B + bb];
                             const uint32_t takeN = sz < need ? sz : need;
                             const uint64_t mo = (uint64_t)bb * A.mstride;
                             for (uint32_t j = lane; j < takeN; j += 64) {
@@ -1278,8 +1278,8 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.mem = ix.mem;
     a.cmg = ix.cmg;
     a.N = ix.N;
-    a.q0 = (uint32_t)(ix.N / ix.p.B);
-    a.rem = (uint32_t)(ix.N % ix.p.B);
+    a.gsize = ix.gsize;
+    a.gmax = ix.gmax;
     a.L = ix.p.L;
     a.R = ix.p.R;
     a.Rp = ix.Rp;

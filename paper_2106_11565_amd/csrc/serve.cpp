@@ -337,9 +337,13 @@ static void launch(Server &S, Lane &ln) {
     uint32_t *codes = reinterpret_cast<uint32_t *>(base + pl.codes);
     uint32_t *out = reinterpret_cast<uint32_t *>(base + pl.out);
     Arena ws{base + pl.hash, pl.total - pl.hash, 0};
-    hash_batch(ix, in, codes, s, nullptr, dense ? -1.0 : (double)ln.nitems / (double)nq, &ws);
-    query_launch(ix, codes, nq, k, out, out + nq * k, S.cfg.persistent != 0, s,
-                 reinterpret_cast<uint32_t *>(base + pl.work));
+    {
+        // one index version per batch (an insert swaps arrays in between)
+        std::shared_lock<std::shared_mutex> rl(ix.rw);
+        hash_batch(ix, in, codes, s, nullptr, dense ? -1.0 : (double)ln.nitems / (double)nq, &ws);
+        query_launch(ix, codes, nq, k, out, out + nq * k, S.cfg.persistent != 0, s,
+                     reinterpret_cast<uint32_t *>(base + pl.work));
+    }
     // results: requests with device outputs get their slices copied there,
     // the others share one copy of the whole batch into pinned host memory
     ln.segs.clear();

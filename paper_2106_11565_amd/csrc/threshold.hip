@@ -38,7 +38,8 @@ struct TArgs {
     const uint32_t *mem;
     const uint16_t *cmg;
     uint32_t L, R, Rp, B, Bp, nbits, t, max_out;
-    uint32_t q0, rem, gmax, mstride, cnt_words;
+    const uint32_t *gsize;  // [R][B] members of each cell
+    uint32_t gmax, mstride, cnt_words;
     uint32_t *ids;
     uint32_t *counts;
 };
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(T) void threshold_kernel(TArgs A) {
                 if (i < items) {
                     const uint32_t ci = (uint32_t)(i / A.gmax);
                     const uint32_t cb = lb[ci], j = (uint32_t)(i - (uint64_t)ci * A.gmax);
-                    const uint32_t sz = A.q0 + (cb < A.rem ? 1u : 0u);
+                    const uint32_t sz = A.gsize[rep * B + cb];
                     if (j < sz) {
                         const uint64_t slot = (uint64_t)cb * A.mstride + j;
                         x = memr[slot];
@@ -203,9 +204,8 @@ void threshold_launch(const Index &ix, const uint32_t *codes_dev, uint64_t nq, u
     a.nbits = ix.nbits;
     a.t = t;
     a.max_out = max_out;
-    a.q0 = (uint32_t)(ix.N / ix.p.B);
-    a.rem = (uint32_t)(ix.N % ix.p.B);
-    a.gmax = a.q0 + (a.rem ? 1u : 0u);
+    a.gsize = ix.gsize;
+    a.gmax = ix.gmax;
     a.mstride = ix.mstride;
     a.cnt_words = (uint32_t)((((size_t)a.R * a.Bp) / 4 + 3) & ~(size_t)3);
     a.ids = ids_dev;

@@ -87,6 +87,25 @@ typedef struct flinng_input {
     uint32_t reserved;        /* must be 0                                    */
 } flinng_input;
 
+/* A batch of symbol sequences to be read as sets of n-grams (the paper
+ * hashes genome reads and URLs as n-gram sets, Section 7, Datasets).  The
+ * item set of a sequence is, for every window of `gram` consecutive symbols,
+ * the window's base-`radix` value v = sum_i s_{p+i} radix^(gram-1-i) mixed
+ * with `key`: MurmurHash3's 64-bit finaliser of (v XOR key) for an index of
+ * 64-bit items, its 32-bit finaliser of (low 32 bits of v) XOR (low 32 bits
+ * of key) for 32-bit items.  A sequence shorter than `gram` is the empty
+ * set.  Symbols must be below `radix`. */
+typedef struct flinng_text {
+    const uint8_t *symbols;   /* concatenated sequences, one symbol per byte  */
+    const uint64_t *offsets;  /* count+1 nondecreasing offsets into symbols   */
+    uint64_t count;           /* number of sequences                          */
+    uint64_t key;             /* item key                                     */
+    uint32_t gram;            /* n-gram length >= 1, radix^gram <= 2^64        */
+    uint32_t radix;           /* alphabet size, 2..256                        */
+    uint32_t on_device;       /* 1: symbols and offsets are device pointers   */
+    uint32_t reserved;        /* must be 0                                    */
+} flinng_text;
+
 typedef struct flinng_index flinng_index;
 
 /* Facts about a built index (sizes in elements unless noted). */
@@ -139,6 +158,22 @@ int flinng_build(const flinng_params *p, const flinng_input *data,
 int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k,
                  uint32_t *ids, uint32_t *scores, uint32_t out_on_device,
                  uint32_t persistent, void *stream);
+
+/*
+ * flinng_build_text / flinng_query_text -- flinng_build and flinng_query
+ * for MinHash indexes whose points and queries arrive as symbol sequences
+ * (flinng_text): the n-gram items are extracted and mixed on the device,
+ * then hashed, indexed and queried exactly as the same items given as sets
+ * (an index built from sets answers text queries and vice versa, when the
+ * items agree).  For device text the calls read two offsets back to size
+ * the item buffer.  FLINNG_EINVAL for a dense index, radix outside 2..256,
+ * gram 0, radix^gram above 2^64, or what flinng_build / flinng_query reject.
+ */
+int flinng_build_text(const flinng_params *p, const flinng_text *data,
+                      void *stream, flinng_index **out);
+int flinng_query_text(const flinng_index *idx, const flinng_text *q, uint32_t k,
+                      uint32_t *ids, uint32_t *scores, uint32_t out_on_device,
+                      uint32_t persistent, void *stream);
 
 /*
  * flinng_query_codes -- the count + threshold + decode stage alone, for
@@ -369,6 +404,18 @@ int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot,
 int flinng_serve_submit_to(flinng_server *srv, uint32_t idx_slot,
                            const flinng_input *q, uint32_t k, uint32_t *ids,
                            uint32_t *scores, uint64_t *ticket);
+
+/* Submit a request of symbol sequences (flinng_text, for a MinHash index
+ * slot): the batch extracts their n-gram items on the device, so no host
+ * preprocessing stands in the served path.  Host text is copied before
+ * return; device text is borrowed until the request completes.  ids and
+ * scores: device buffers (count*k each; scores may be NULL) as in
+ * flinng_serve_submit_to, or both NULL to take the results with
+ * flinng_serve_wait.  Requests are batched with others of the same slot, k
+ * and text parameters. */
+int flinng_serve_submit_text(flinng_server *srv, uint32_t idx_slot,
+                             const flinng_text *q, uint32_t k, uint32_t *ids,
+                             uint32_t *scores, uint64_t *ticket);
 
 /* Wait for a request and release the ticket.  Requests submitted with
  * flinng_serve_submit: copies the results (count*k each) into the host

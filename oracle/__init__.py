@@ -13,7 +13,7 @@ Every function names the passage of the paper it follows; each is pinned by
 """
 from .core import (  # noqa: F401
     build_lib, lib, sm64, mix64, hyperplanes, srp_codes, exact_dot_sign,
-    minhash_codes, permute, groups, stream_groups, members, build_lists, counts,
+    minhash_codes, text_items, permute, groups, stream_groups, members, build_lists, counts,
     counts_brute, decode, query_fixed_t, set_threads, get_threads, OracleIndex,
     bf16_to_f64, SRP_F32, SRP_BF16, MINHASH_U32, MINHASH_U64,
 )

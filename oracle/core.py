@@ -48,6 +48,7 @@ def _bind(L):
         "or_srp_codes": (u64, [vp, u64, u32, vp, u32, u32, vp]),
         "or_exact_dot_sign": (ctypes.c_int, [vp, vp, u32]),
         "or_minhash_codes": (None, [vp, vp, u64, u64, u32, u32, u32, vp]),
+        "or_text_items": (u64, [vp, vp, u64, u32, u32, u64, u32, vp, vp]),
         "or_permute": (u64, [u64, u32, u64, u64]),
         "or_groups": (None, [u64, u32, u32, u64, vp]),
         "or_members": (None, [vp, u64, u32, u32, vp, vp]),
@@ -125,6 +126,23 @@ def minhash_codes(items, offsets, seed, K, L, b):
         items = np.zeros(1, dtype=np.uint64)
     lib().or_minhash_codes(_p(items), _p(offsets), n, seed, K, L, b, _p(codes))
     return codes
+
+
+def text_items(symbols, offsets, gram, radix, key, item_bits):
+    """Item sets (CSR, uint64 / uint32 per item_bits) of symbol sequences read
+    as n-grams: each window's base-radix value mixed with the key."""
+    sym = np.ascontiguousarray(symbols, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.shape[0] - 1
+    cap = max(1, int(off[-1] - off[0]) if n else 1)
+    items = np.empty(cap, dtype=np.uint64)
+    ioff = np.empty(n + 1, dtype=np.uint64)
+    if sym.size == 0:
+        sym = np.zeros(1, dtype=np.uint8)
+    m = lib().or_text_items(_p(sym), _p(off), n, gram, radix, int(key) & (2**64 - 1), item_bits,
+                            _p(items), _p(ioff))
+    items = items[:m].copy()
+    return (items if item_bits == 64 else items.astype(np.uint32)), ioff
 
 
 def permute(N, r, seed, x):

@@ -183,6 +183,55 @@ void or_minhash_codes(const uint64_t *items, const uint64_t *offsets, uint64_t n
 }
 
 /* ------------------------------------------------------------------------- */
+/* N-gram item sets of symbol sequences (the paper hashes genome reads and URLs
+ * as n-gram sets, Section 7, "Datasets").  Sequence s is the set of its
+ * windows of `gram` symbols; a window's value is its base-`radix` number
+ * v = sum_i s[p+i] radix^(gram-1-i), and its item is MurmurHash3's 64-bit
+ * finaliser of (v XOR key) (item_bits 64) or its 32-bit finaliser of
+ * (low32(v) XOR low32(key)) (item_bits 32) (Austin Appleby, MurmurHash3,
+ * public domain).  Sequences shorter than gram have no items.  Items are
+ * returned as uint64 (32-bit ones zero-extended), CSR by sequence.         */
+static uint64_t or_murmur64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xFF51AFD7ED558CCDULL;
+    k ^= k >> 33;
+    k *= 0xC4CEB9FE1A85EC53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+static uint32_t or_murmur32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6BU;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35U;
+    h ^= h >> 16;
+    return h;
+}
+
+uint64_t or_text_items(const uint8_t *sym, const uint64_t *off, uint64_t n,
+                       uint32_t gram, uint32_t radix, uint64_t key,
+                       uint32_t item_bits, uint64_t *items, uint64_t *item_off)
+{
+    uint64_t m = 0;
+    for (uint64_t s = 0; s < n; ++s) {
+        item_off[s] = m;
+        const uint64_t len = off[s + 1] - off[s];
+        for (uint64_t p = 0; p + gram <= len; ++p) {
+            uint64_t v = 0;
+            for (uint32_t i = 0; i < gram; ++i)
+                v = v * radix + sym[off[s] + p + i];
+            items[m++] = item_bits == 64 ? or_murmur64(v ^ key)
+                                         : (uint64_t)or_murmur32((uint32_t)v ^ (uint32_t)key);
+        }
+    }
+    item_off[n] = m;
+    return m;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Group assignment (Algorithm 1, Index Construction): in repetition r the
  * points are permuted by a random permutation P_r and point x joins group
  * P_r(x) mod B, so each group holds floor(N/B) or ceil(N/B) points.

@@ -11,7 +11,8 @@ import numpy as np
 
 from ._lib import (  # noqa: F401
     SRP_F32, SRP_BF16, MINHASH_U32, MINHASH_U64, FlinngError, Params, Input,
-    IndexInfo, ServeConfig, ServeStats, Theory, check, lib, make_input, current_stream,
+    IndexInfo, ServeConfig, ServeStats, Theory, Text, check, lib, make_input, make_text,
+    current_stream,
     EBUSY, EINVAL, ENOMEM, ETIMEDOUT, ESTATE,
 )
 
@@ -35,19 +36,26 @@ def _stream(stream):
 
 
 class Index:
-    """A FLINNG index resident on the current HIP device (flinng_build)."""
+    """A FLINNG index resident on the current HIP device (flinng_build).
+    text=(gram, radix, key): `data` is (symbols, offsets) of symbol
+    sequences read as n-gram sets (flinng_build_text)."""
 
     def __init__(self, data, family, K, L, R, B, seed, dim=None, bucket_bits=0,
-                 stream=None):
+                 stream=None, text=None):
         self.family = family
         p = Params(family=family, K=K, L=L, R=R, B=B, bucket_bits=bucket_bits,
                    reserved=0, seed=seed)
         if family in (SRP_F32, SRP_BF16):
             p.dim = dim if dim is not None else data.shape[1]
-        inp, keep = make_input(data, family)
         h = ctypes.c_void_p()
-        check(lib().flinng_build(ctypes.byref(p), ctypes.byref(inp), _stream(stream),
-                                 ctypes.byref(h)))
+        if text is not None:
+            t, keep = make_text(data, *text)
+            check(lib().flinng_build_text(ctypes.byref(p), ctypes.byref(t), _stream(stream),
+                                          ctypes.byref(h)))
+        else:
+            inp, keep = make_input(data, family)
+            check(lib().flinng_build(ctypes.byref(p), ctypes.byref(inp), _stream(stream),
+                                     ctypes.byref(h)))
         self._h = h
         del keep
 
@@ -86,6 +94,25 @@ class Index:
         sc = np.empty((nq, k), dtype=np.uint32)
         check(lib().flinng_query(self._h, ctypes.byref(inp), k, ids.ctypes.data,
                                  sc.ctypes.data, 0, int(persistent), _stream(stream)))
+        del keep
+        return ids, sc
+
+    def query_text(self, seqs, text, k, persistent=False, stream=None, out=None):
+        """flinng_query_text: queries given as symbol sequences (symbols,
+        offsets) with text=(gram, radix, key); host results unless out=(ids,
+        scores) device tensors are given."""
+        t, keep = make_text(seqs, *text)
+        nq = t.count
+        if out is not None:
+            ids_t, sc_t = out
+            check(lib().flinng_query_text(self._h, ctypes.byref(t), k, ids_t.data_ptr(),
+                                          sc_t.data_ptr() if sc_t is not None else None, 1,
+                                          int(persistent), _stream(stream)))
+            return out
+        ids = np.empty((nq, k), dtype=np.uint32)
+        sc = np.empty((nq, k), dtype=np.uint32)
+        check(lib().flinng_query_text(self._h, ctypes.byref(t), k, ids.ctypes.data, sc.ctypes.data,
+                                      0, int(persistent), _stream(stream)))
         del keep
         return ids, sc
 
@@ -186,6 +213,20 @@ class Server:
                                            sc_t.data_ptr() if sc_t is not None else None,
                                            ctypes.byref(t)))
         return t.value, int(inp.count)
+
+    def submit_text(self, slot, seqs, text, k, out=None):
+        """flinng_serve_submit_text: symbol sequences with text=(gram, radix,
+        key); results into out=(ids, scores) device tensors (then complete
+        with wait_done) or, without out, taken with wait."""
+        t, keep = make_text(seqs, *text)
+        tk = ctypes.c_uint64()
+        ip = sp = None
+        if out is not None:
+            ip = out[0].data_ptr()
+            sp = out[1].data_ptr() if out[1] is not None else None
+        check(lib().flinng_serve_submit_text(self._h, slot, ctypes.byref(t), k, ip, sp,
+                                             ctypes.byref(tk)))
+        return tk.value, int(t.count)
 
     def wait_done(self, ticket, timeout_ns=-1):
         """Wait for a request submitted with submit_to."""

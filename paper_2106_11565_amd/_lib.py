@@ -36,6 +36,11 @@ class Input(ctypes.Structure):
                 ("on_device", c_u32), ("reserved", c_u32)]
 
 
+class Text(ctypes.Structure):
+    _fields_ = [("symbols", c_vp), ("offsets", c_vp), ("count", c_u64), ("key", c_u64),
+                ("gram", c_u32), ("radix", c_u32), ("on_device", c_u32), ("reserved", c_u32)]
+
+
 class IndexInfo(ctypes.Structure):
     _fields_ = [("N", c_u64), ("list_entries", c_u64), ("device_bytes", c_u64),
                 ("family", c_u32), ("dim", c_u32), ("K", c_u32), ("L", c_u32),
@@ -80,6 +85,10 @@ def lib():
         P = ctypes.POINTER
         sig = {
             "flinng_build": (ctypes.c_int, [P(Params), P(Input), c_vp, P(c_vp)]),
+            "flinng_build_text": (ctypes.c_int, [P(Params), P(Text), c_vp, P(c_vp)]),
+            "flinng_query_text": (ctypes.c_int, [c_vp, P(Text), c_u32, c_vp, c_vp, c_u32, c_u32, c_vp]),
+            "flinng_serve_submit_text": (ctypes.c_int, [c_vp, c_u32, P(Text), c_u32, c_vp, c_vp,
+                                                        P(c_u64)]),
             "flinng_query": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_u32, c_vp]),
             "flinng_query_codes": (ctypes.c_int, [c_vp, c_vp, c_u64, c_u32, c_vp, c_vp, c_u32, c_vp, c_vp]),
             "flinng_query_noalloc": (ctypes.c_int, [c_vp, P(Input), c_u32, c_vp, c_vp, c_u32, c_vp]),
@@ -165,6 +174,27 @@ def make_input(data, family):
             inp.count, inp.on_device = of.shape[0] - 1, 0
             keep += [it, of]
     return inp, keep
+
+
+def make_text(seqs, gram, radix, key):
+    """Marshal symbol sequences (symbols uint8, offsets) into a Text.  numpy
+    arrays are host inputs; CUDA torch tensors are device inputs.  Returns
+    (Text, keepalive)."""
+    sym, offs = seqs
+    t = Text(gram=gram, radix=radix, key=int(key) & (2**64 - 1), reserved=0)
+    keep = []
+    if _is_torch(sym):
+        assert sym.is_cuda and offs.is_cuda
+        t.symbols, t.offsets, t.count, t.on_device = sym.data_ptr(), offs.data_ptr(), offs.shape[0] - 1, 1
+        keep += [sym, offs]
+    else:
+        s = np.ascontiguousarray(sym, dtype=np.uint8)
+        o = np.ascontiguousarray(offs, dtype=np.uint64)
+        if s.size == 0:
+            s = np.zeros(1, dtype=np.uint8)
+        t.symbols, t.offsets, t.count, t.on_device = s.ctypes.data, o.ctypes.data, o.shape[0] - 1, 0
+        keep += [s, o]
+    return t, keep
 
 
 def current_stream():

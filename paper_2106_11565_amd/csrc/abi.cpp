@@ -140,63 +140,84 @@ extern "C" {
 
 const char *flinng_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+static void build_impl(const flinng_params *p, const flinng_input *data, hipStream_t s,
+                       flinng_index **out) {
+    require(p && data && out, "NULL argument");
+    *out = nullptr;
+    validate_input(data, p->family, "data");
+    validate_params(*p, data->count);
+    Index *ix = new Index();
+    try {
+        ix->p = *p;
+        ix->N = data->count;
+        FL_HIP(hipGetDevice(&ix->device));
+        const bool dense = is_dense(p->family);
+        ix->nbits = dense ? p->K : p->bucket_bits;
+        if (dense) ix->p.bucket_bits = p->K;
+        ix->dpad = dense ? ((p->dim + 31) / 32) * 32 : 0;
+        ix->Rp = 1;
+        while (ix->Rp < p->R) ix->Rp <<= 1;
+        const uint32_t Bp = (p->B + 3) & ~3u;
+        ix->cell_bytes = ((uint64_t)p->R * Bp <= 65536) ? 2 : 4;
+        const uint64_t N = ix->N;
+        uint64_t bytes = 0;
+        ix->N0 = N;
+        ix->grp_cap = N;
+        ix->grp = dmalloc<uint16_t>(N * ix->Rp, bytes);
+        ix->gsize = dmalloc<uint32_t>((uint64_t)p->R * p->B, bytes);
+        const uint64_t gmax = (N + p->B - 1) / p->B;
+        ix->mstride = (uint32_t)((gmax + 3) & ~3ull);
+        ix->mem = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
+        ix->cmg = dmalloc<uint16_t>((uint64_t)p->R * p->B * ix->mstride * ix->Rp, bytes);
+        if (dense) {
+            ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
+            ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);
+            srp_make_hyperplanes(*ix, s);
+        }
+        // hash all points (in chunks to bound scratch memory)
+        DevBuf codes(N * p->L * 4, s);
+        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix->dpad * 16))
+                                     : (1ull << 20);
+        for (uint64_t b0 = 0; b0 < N; b0 += chunk) {
+            const uint64_t n = std::min(chunk, N - b0);
+            flinng_input part = slice(*data, *ix, b0, n);
+            uint64_t ctr[2] = {0, 0};
+            hash_batch(*ix, part, codes.as<uint32_t>() + b0 * p->L, s, dense ? ctr : nullptr);
+            ix->srp_rechecked += ctr[0];
+            ix->srp_exact += ctr[1];
+        }
+        build_groups(*ix, s);
+        build_lists(*ix, codes.as<uint32_t>(), s);
+        FL_HIP(hipStreamSynchronize(s));
+        ix->device_bytes = index_device_bytes(*ix);
+    } catch (...) {
+        free_index(ix);
+        throw;
+    }
+    *out = reinterpret_cast<flinng_index *>(ix);
+}
+
+extern "C" {
+
 int flinng_build(const flinng_params *p, const flinng_input *data, void *stream,
                  flinng_index **out) {
+    return guard([&] { build_impl(p, data, static_cast<hipStream_t>(stream), out); });
+}
+
+int flinng_build_text(const flinng_params *p, const flinng_text *data, void *stream,
+                      flinng_index **out) {
     return guard([&] {
         require(p && data && out, "NULL argument");
         *out = nullptr;
-        validate_input(data, p->family, "data");
-        validate_params(*p, data->count);
+        validate_text(data, p->family);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        Index *ix = new Index();
-        try {
-            ix->p = *p;
-            ix->N = data->count;
-            FL_HIP(hipGetDevice(&ix->device));
-            const bool dense = is_dense(p->family);
-            ix->nbits = dense ? p->K : p->bucket_bits;
-            if (dense) ix->p.bucket_bits = p->K;
-            ix->dpad = dense ? ((p->dim + 31) / 32) * 32 : 0;
-            ix->Rp = 1;
-            while (ix->Rp < p->R) ix->Rp <<= 1;
-            const uint32_t Bp = (p->B + 3) & ~3u;
-            ix->cell_bytes = ((uint64_t)p->R * Bp <= 65536) ? 2 : 4;
-            const uint64_t N = ix->N;
-            uint64_t bytes = 0;
-            ix->N0 = N;
-            ix->grp_cap = N;
-            ix->grp = dmalloc<uint16_t>(N * ix->Rp, bytes);
-            ix->gsize = dmalloc<uint32_t>((uint64_t)p->R * p->B, bytes);
-            const uint64_t gmax = (N + p->B - 1) / p->B;
-            ix->mstride = (uint32_t)((gmax + 3) & ~3ull);
-            ix->mem = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
-            ix->cmg = dmalloc<uint16_t>((uint64_t)p->R * p->B * ix->mstride * ix->Rp, bytes);
-            if (dense) {
-                ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
-                ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);
-                srp_make_hyperplanes(*ix, s);
-            }
-            // hash all points (in chunks to bound scratch memory)
-            DevBuf codes(N * p->L * 4, s);
-            const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix->dpad * 16))
-                                         : (1ull << 20);
-            for (uint64_t b0 = 0; b0 < N; b0 += chunk) {
-                const uint64_t n = std::min(chunk, N - b0);
-                flinng_input part = slice(*data, *ix, b0, n);
-                uint64_t ctr[2] = {0, 0};
-                hash_batch(*ix, part, codes.as<uint32_t>() + b0 * p->L, s, dense ? ctr : nullptr);
-                ix->srp_rechecked += ctr[0];
-                ix->srp_exact += ctr[1];
-            }
-            build_groups(*ix, s);
-            build_lists(*ix, codes.as<uint32_t>(), s);
-            FL_HIP(hipStreamSynchronize(s));
-            ix->device_bytes = index_device_bytes(*ix);
-        } catch (...) {
-            free_index(ix);
-            throw;
-        }
-        *out = reinterpret_cast<flinng_index *>(ix);
+        const uint64_t nsym = text_symbols(*data);
+        Scratch sc(nullptr, s);
+        flinng_input items{};
+        text_to_items(*data, p->family, nsym, s, sc, &items);
+        build_impl(p, &items, s, out);
     });
 }
 
@@ -289,37 +310,62 @@ static uint32_t *codes_scratch(const Index &ix, hipStream_t s, size_t bytes) {
     return static_cast<uint32_t *>(p);
 }
 
+}  // extern "C"
+
+static void query_impl(const flinng_index *idx, const flinng_input *q, uint32_t k, uint32_t *ids,
+                       uint32_t *scores, uint32_t out_on_device, uint32_t persistent,
+                       void *stream) {
+    require(idx != nullptr, "index is NULL");
+    const Index &ix = *reinterpret_cast<const Index *>(idx);
+    validate_input(q, ix.p.family, "queries");
+    require(ids != nullptr, "ids is NULL");
+    require(k >= 1 && k <= query_max_k(), "k must be in 1..4096");
+    const uint64_t nq = q->count;
+    if (nq == 0) return;
+    FL_HIP(hipSetDevice(ix.device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::shared_lock<std::shared_mutex> rl(ix.rw);  // one index version per call
+    std::unique_lock<std::mutex> lock(ix.scratch_mu);
+    uint32_t *codes = codes_scratch(ix, s, (size_t)nq * ix.p.L * 4);
+    hash_batch(ix, *q, codes, s, nullptr);
+    DevBuf work(persistent ? 4 : 0, s);
+    if (out_on_device) {
+        query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>());
+        lock.unlock();
+        rl.unlock();
+    } else {
+        DevBuf dids(nq * k * 4, s), dsc(scores ? nq * k * 4 : 0, s);
+        query_launch(ix, codes, nq, k, dids.as<uint32_t>(), scores ? dsc.as<uint32_t>() : nullptr,
+                     persistent != 0, s, work.as<uint32_t>());
+        lock.unlock();
+        rl.unlock();
+        FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
+        if (scores) FL_HIP(hipMemcpyAsync(scores, dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
+        FL_HIP(hipStreamSynchronize(s));
+    }
+}
+
+extern "C" {
+
 int flinng_query(const flinng_index *idx, const flinng_input *q, uint32_t k, uint32_t *ids,
                  uint32_t *scores, uint32_t out_on_device, uint32_t persistent, void *stream) {
+    return guard([&] { query_impl(idx, q, k, ids, scores, out_on_device, persistent, stream); });
+}
+
+int flinng_query_text(const flinng_index *idx, const flinng_text *q, uint32_t k, uint32_t *ids,
+                      uint32_t *scores, uint32_t out_on_device, uint32_t persistent, void *stream) {
     return guard([&] {
         require(idx != nullptr, "index is NULL");
         const Index &ix = *reinterpret_cast<const Index *>(idx);
-        validate_input(q, ix.p.family, "queries");
-        require(ids != nullptr, "ids is NULL");
-        require(k >= 1 && k <= query_max_k(), "k must be in 1..4096");
-        const uint64_t nq = q->count;
-        if (nq == 0) return;
+        validate_text(q, ix.p.family);
+        if (q->count == 0) return;
         FL_HIP(hipSetDevice(ix.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
-        std::shared_lock<std::shared_mutex> rl(ix.rw);  // one index version per call
-        std::unique_lock<std::mutex> lock(ix.scratch_mu);
-        uint32_t *codes = codes_scratch(ix, s, (size_t)nq * ix.p.L * 4);
-        hash_batch(ix, *q, codes, s, nullptr);
-        DevBuf work(persistent ? 4 : 0, s);
-        if (out_on_device) {
-            query_launch(ix, codes, nq, k, ids, scores, persistent != 0, s, work.as<uint32_t>());
-            lock.unlock();
-            rl.unlock();
-        } else {
-            DevBuf dids(nq * k * 4, s), dsc(scores ? nq * k * 4 : 0, s);
-            query_launch(ix, codes, nq, k, dids.as<uint32_t>(), scores ? dsc.as<uint32_t>() : nullptr,
-                         persistent != 0, s, work.as<uint32_t>());
-            lock.unlock();
-            rl.unlock();
-            FL_HIP(hipMemcpyAsync(ids, dids.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
-            if (scores) FL_HIP(hipMemcpyAsync(scores, dsc.ptr, nq * k * 4, hipMemcpyDeviceToHost, s));
-            FL_HIP(hipStreamSynchronize(s));
-        }
+        const uint64_t nsym = text_symbols(*q);
+        Scratch sc(nullptr, s);
+        flinng_input items{};
+        text_to_items(*q, ix.p.family, nsym, s, sc, &items);
+        query_impl(idx, &items, k, ids, scores, out_on_device, persistent, stream);
     });
 }
 

@@ -207,7 +207,22 @@ void hash_batch(const Index &ix, const flinng_input &in, uint32_t *codes_dev,
                 Arena *ws = nullptr);
 // Device bytes one served batch of nq queries (nitems set items) occupies:
 // staged input, codes, results and hash scratch, as the server carves them.
-uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k);
+uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k,
+                            bool text);
+
+// N-gram text (text.hip).  validate_text: argument checks (FLINNG_EINVAL);
+// text_symbols: symbols the sequences span (reads two offsets back for a
+// device input); text_to_items: the item sets on the device (buffers from
+// sc), described by a device flinng_input of the family's item type.
+void validate_text(const flinng_text *t, uint32_t family);
+uint64_t text_symbols(const flinng_text &t);
+void text_to_items(const flinng_text &t, uint32_t family, uint64_t nsym, hipStream_t s,
+                   Scratch &sc, flinng_input *out);
+// Device bytes text_to_items takes from an arena for n sequences of nsym symbols.
+inline size_t text_scratch_bytes(uint32_t family, uint64_t n, uint64_t nsym) {
+    const size_t isz = family == FLINNG_MINHASH_U64 ? 8 : 4;
+    return Arena::round((n + 1) * 8) + Arena::round((nsym ? nsym : 1) * isz);
+}
 
 // Segment copies by kernel (stage.hip): each segment copies `bytes` from
 // src to dst, both device-visible addresses (device memory, or mapped pinned

@@ -48,11 +48,15 @@ struct BatchPlan {
     size_t codes = 0, out = 0, work = 0, hash = 0, total = 0;
 };
 
-static BatchPlan plan_batch(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k) {
+// nitems: set items, or symbols of text requests (one byte each; their
+// n-gram items are extracted into the hash scratch).
+static BatchPlan plan_batch(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k,
+                            bool text = false) {
     BatchPlan b;
     const bool dense = is_dense(ix.p.family);
     const size_t vbytes = dense ? nq * (size_t)ix.p.dim * (ix.p.family == FLINNG_SRP_F32 ? 4 : 2)
-                                : nitems * (ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4);
+                          : text ? nitems
+                                 : nitems * (ix.p.family == FLINNG_MINHASH_U64 ? 8 : 4);
     b.offs = (vbytes + 7) & ~(size_t)7;
     b.in_bytes = dense ? vbytes : b.offs + (nq + 1) * 8;
     size_t o = 0;
@@ -66,12 +70,13 @@ static BatchPlan plan_batch(const Index &ix, uint64_t nq, uint64_t nitems, uint3
     o += Arena::round(4);
     b.hash = o;
     o += dense ? srp_scratch_bytes(ix, nq) : 0;
+    o += text ? text_scratch_bytes(ix.p.family, nq, nitems) : 0;
     b.total = o;
     return b;
 }
 
-uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k) {
-    return plan_batch(ix, nq, nitems, k).total;
+uint64_t batch_device_bytes(const Index &ix, uint64_t nq, uint64_t nitems, uint32_t k, bool text) {
+    return plan_batch(ix, nq, nitems, k, text).total;
 }
 
 // Pinned host memory mapped into the device's address space, coherent, so
@@ -153,6 +158,9 @@ struct Request {
     std::vector<unsigned char> values;  // small payloads (or the pool is full)
     Pinned pinned;                       // large payloads: a block of the pool
     uint64_t dev_values = 0;             // device-resident payload (borrowed)
+    bool text = false;                   // symbol sequences (payload: symbols)
+    uint32_t gram = 0, radix = 0;
+    uint64_t tkey = 0, nwin = 0;         // item key; n-gram windows
     uint32_t *out_ids = nullptr;         // device outputs (borrowed), or null:
     uint32_t *out_scores = nullptr;      // results are kept for wait()
     int pcls = -1;
@@ -337,10 +345,28 @@ static void launch(Server &S, Lane &ln) {
     uint32_t *codes = reinterpret_cast<uint32_t *>(base + pl.codes);
     uint32_t *out = reinterpret_cast<uint32_t *>(base + pl.out);
     Arena ws{base + pl.hash, pl.total - pl.hash, 0};
+    double mean_hint = dense ? -1.0 : (double)ln.nitems / (double)nq;
+    if (ln.reqs[0]->text) {
+        // the staged symbols become n-gram items in the hash scratch
+        const Request &h = *ln.reqs[0];
+        flinng_text t{};
+        t.symbols = static_cast<const uint8_t *>(in.values);
+        t.offsets = in.offsets;
+        t.count = nq;
+        t.key = h.tkey;
+        t.gram = h.gram;
+        t.radix = h.radix;
+        t.on_device = 1;
+        Scratch sc(&ws, s);
+        text_to_items(t, ix.p.family, ln.nitems, s, sc, &in);
+        uint64_t nwin = 0;
+        for (const Request *r : ln.reqs) nwin += r->nwin;
+        mean_hint = (double)nwin / (double)nq;
+    }
     {
         // one index version per batch (an insert swaps arrays in between)
         std::shared_lock<std::shared_mutex> rl(ix.rw);
-        hash_batch(ix, in, codes, s, nullptr, dense ? -1.0 : (double)ln.nitems / (double)nq, &ws);
+        hash_batch(ix, in, codes, s, nullptr, mean_hint, &ws);
         query_launch(ix, codes, nq, k, out, out + nq * k, S.cfg.persistent != 0, s,
                      reinterpret_cast<uint32_t *>(base + pl.work));
     }
@@ -449,20 +475,23 @@ static void scheduler(Server *Sp) {
             uint64_t nq = 0, nitems = 0;
             for (auto it = S.queue.begin(); it != S.queue.end();) {
                 Request *r = *it;
-                if (r->slot != head->slot || r->k != head->k) {
+                if (r->slot != head->slot || r->k != head->k || r->text != head->text ||
+                    (r->text && (r->gram != head->gram || r->radix != head->radix ||
+                                 r->tkey != head->tkey))) {
                     ++it;
                     continue;
                 }
                 if (!take.empty() && nq + r->nq > S.cfg.max_batch) break;
                 if (!take.empty() &&
-                    batch_device_bytes(ix, nq + r->nq, nitems + r->nitems, head->k) > allowed)
+                    batch_device_bytes(ix, nq + r->nq, nitems + r->nitems, head->k, head->text) >
+                        allowed)
                     break;
                 take.push_back(r);
                 nq += r->nq;
                 nitems += r->nitems;
                 it = S.queue.erase(it);
             }
-            const BatchPlan plan = plan_batch(ix, nq, nitems, head->k);
+            const BatchPlan plan = plan_batch(ix, nq, nitems, head->k, head->text);
             if (S.cfg.linger_ns && nq < S.cfg.max_batch) {
                 // not full: hold it until the oldest request has lingered long enough
                 const auto until = head->t_submit + std::chrono::nanoseconds(S.cfg.linger_ns);
@@ -610,6 +639,25 @@ int flinng_serve_create(flinng_index *const *indexes, uint32_t n_idx, const flin
 
 namespace flinng {
 
+// Queue a request (common tail of both submit paths).
+static void enqueue(Server &S, std::unique_ptr<Request> r, uint64_t *ticket) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stop) fail(FLINNG_ESTATE, "server is shutting down");
+    if (r->mem > S.cfg.mem_budget || S.queue.size() >= S.cfg.max_queue) {
+        S.rejected++;
+        fail(FLINNG_EBUSY, r->mem > S.cfg.mem_budget ? "request exceeds the memory budget"
+                                                     : "queue full");
+    }
+    Request *rp = r.release();
+    rp->ticket = S.next_ticket++;
+    rp->t_submit = Clock::now();
+    S.tickets[rp->ticket] = rp;
+    S.queue.push_back(rp);
+    S.submitted++;
+    *ticket = rp->ticket;
+    S.cv_sched.notify_one();
+}
+
 // Submit one request (both ABI entry points).  Host inputs are copied;
 // device inputs are borrowed until the request completes (set offsets are
 // read back once, here, to size the batch).  out_ids/out_scores: device
@@ -668,27 +716,72 @@ static void submit_request(Server &S, uint32_t idx_slot, const flinng_input *q, 
             r->set_payload(v, r->nitems * isz);
         }
     }
-    r->mem = batch_device_bytes(ix, r->nq, r->nitems, k);
-    std::lock_guard<std::mutex> lk(S.mu);
-    if (S.stop) fail(FLINNG_ESTATE, "server is shutting down");
-    if (r->mem > S.cfg.mem_budget || S.queue.size() >= S.cfg.max_queue) {
-        S.rejected++;
-        fail(FLINNG_EBUSY, r->mem > S.cfg.mem_budget ? "request exceeds the memory budget"
-                                                     : "queue full");
+    r->mem = batch_device_bytes(ix, r->nq, r->nitems, k, false);
+    enqueue(S, std::move(r), ticket);
+}
+
+// A request of symbol sequences: the payload is the symbols (host copy or
+// borrowed device range), offsets rebased on the host.
+static void submit_text_request(Server &S, uint32_t idx_slot, const flinng_text *q, uint32_t k,
+                                uint32_t *out_ids, uint32_t *out_scores, uint64_t *ticket) {
+    if (!ticket) fail(FLINNG_EINVAL, "NULL argument");
+    if (idx_slot >= S.idx.size()) fail(FLINNG_EINVAL, "bad index slot");
+    const Index &ix = *S.idx[idx_slot];
+    validate_text(q, ix.p.family);
+    if (k < 1 || k > query_max_k()) fail(FLINNG_EINVAL, "k must be in 1..4096");
+    if (q->count == 0) fail(FLINNG_EINVAL, "empty request");
+    std::unique_ptr<Request> r(new Request());
+    r->pool = &S.pool;
+    r->slot = idx_slot;
+    r->k = k;
+    r->nq = q->count;
+    r->out_ids = out_ids;
+    r->out_scores = out_ids ? out_scores : nullptr;
+    r->text = true;
+    r->gram = q->gram;
+    r->radix = q->radix;
+    r->tkey = q->key;
+    r->offsets.resize(q->count + 1);
+    if (q->on_device) {
+        FL_HIP(hipSetDevice(S.device));
+        FL_HIP(hipMemcpy(r->offsets.data(), q->offsets, (q->count + 1) * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(r->offsets.data(), q->offsets, (q->count + 1) * 8);
     }
-    Request *rp = r.release();
-    rp->ticket = S.next_ticket++;
-    rp->t_submit = Clock::now();
-    S.tickets[rp->ticket] = rp;
-    S.queue.push_back(rp);
-    S.submitted++;
-    *ticket = rp->ticket;
-    S.cv_sched.notify_one();
+    const uint64_t first = r->offsets[0], last = r->offsets[q->count];
+    for (uint64_t i = 0; i <= q->count; ++i) {
+        if (i && r->offsets[i] < r->offsets[i - 1])
+            fail(FLINNG_EINVAL, "text offsets must be nondecreasing");
+        r->offsets[i] -= first;
+        if (i) {
+            const uint64_t len = r->offsets[i] - r->offsets[i - 1];
+            r->nwin += len >= q->gram ? len - q->gram + 1 : 0;
+        }
+    }
+    r->nitems = last - first;
+    if (r->nitems && !q->symbols) fail(FLINNG_EINVAL, "text.symbols is NULL");
+    if (q->on_device) {
+        r->vbytes = r->nitems;
+        r->dev_values = reinterpret_cast<uint64_t>(q->symbols) + first;
+    } else {
+        r->set_payload(q->symbols + first, r->nitems);
+    }
+    r->mem = batch_device_bytes(ix, r->nq, r->nitems, k, true);
+    enqueue(S, std::move(r), ticket);
 }
 
 }  // namespace flinng
 
 extern "C" {
+
+int flinng_serve_submit_text(flinng_server *srv, uint32_t idx_slot, const flinng_text *q,
+                             uint32_t k, uint32_t *ids, uint32_t *scores, uint64_t *ticket) {
+    return sguard([&] {
+        if (!srv) fail(FLINNG_EINVAL, "NULL argument");
+        if (!ids && scores) fail(FLINNG_EINVAL, "scores without ids");
+        submit_text_request(*reinterpret_cast<Server *>(srv), idx_slot, q, k, ids, scores, ticket);
+    });
+}
 
 int flinng_serve_submit(flinng_server *srv, uint32_t idx_slot, const flinng_input *q, uint32_t k,
                         uint64_t *ticket) {

@@ -177,8 +177,20 @@ def _genome_items(A, gram, key, chunk=65536):
     return np.concatenate(items), np.concatenate(offs)
 
 
+def _text_of_rows(A, lens=None):
+    """Symbol sequences (uint8 symbols, offsets) of the rows of A (the first
+    lens[i] symbols of row i, or whole rows)."""
+    if lens is None:
+        return (np.ascontiguousarray(A, dtype=np.uint8).ravel(),
+                np.arange(0, A.shape[0] * A.shape[1] + 1, A.shape[1], dtype=np.uint64))
+    keep = np.arange(A.shape[1])[None, :] < np.asarray(lens)[:, None]
+    offs = np.zeros(A.shape[0] + 1, dtype=np.uint64)
+    np.cumsum(np.asarray(lens, dtype=np.uint64), out=offs[1:])
+    return A[keep].astype(np.uint8), offs
+
+
 def genome(n_base=500_000, read_len=100, gram=20, seed=0, nq=10000, q_seed=2,
-           max_sub=5):
+           max_sub=5, text=False):
     """n_base random reads over {A,C,G,T} plus one mutated copy of each (1..5
     substitutions at distinct positions, each to a different base): ids
     0..n_base-1 are the base reads, n_base+i is the copy of read i.  Each read
@@ -197,6 +209,12 @@ def genome(n_base=500_000, read_len=100, gram=20, seed=0, nq=10000, q_seed=2,
     sq = rq.integers(1, max_sub + 1, len(qbase))
     QA = _substitute(A[qbase], sq, rq, 4)
     qitems, qoffs = _genome_items(QA, gram, key)
+    if text:
+        # the reads themselves (bases 0..3), which the items are the 2-bit
+        # packed n-grams of, mixed with the key
+        extra = {"data": _text_of_rows(np.concatenate([A, C])), "queries": _text_of_rows(QA),
+                 "gram": gram, "radix": 4, "key": int(key)}
+        return items, offs, qitems, qoffs, qbase, extra
     return items, offs, qitems, qoffs, qbase
 
 
@@ -262,7 +280,7 @@ def _url_items(A, lens, key32):
 
 
 def url(n_templates=1_000_000, dups=4, min_len=20, max_len=120, alphabet=40,
-        max_edit=5, seed=0, nq=10000, q_seed=3, chunk=131072):
+        max_edit=5, seed=0, nq=10000, q_seed=3, chunk=131072, text=False):
     """n_templates strings of length U[min_len, max_len] over a 40-symbol
     alphabet, each followed by `dups` near-duplicates made by 1..5 uniform
     random edits: id t*(dups+1) is template t, the next `dups` ids are its
@@ -292,13 +310,13 @@ def url(n_templates=1_000_000, dups=4, min_len=20, max_len=120, alphabet=40,
         SA = np.stack(blocks_A, axis=1).reshape(n * (dups + 1), W)
         SL = np.stack(blocks_L, axis=1).reshape(n * (dups + 1))
         it, of = _url_items(SA, SL, key32)
-        return A, lens, it, of
+        return A, lens, it, of, (_text_of_rows(SA, SL) if text else None)
 
     with ThreadPoolExecutor(_workers()) as ex:
         parts = list(ex.map(block, range((n_templates + chunk - 1) // chunk)))
     items_l, offs_l, base = [], [np.zeros(1, dtype=np.uint64)], np.uint64(0)
     T_all_A, T_all_len = [], []
-    for A, lens, it, of in parts:
+    for A, lens, it, of, _ in parts:
         T_all_A.append(A)
         T_all_len.append(lens)
         items_l.append(it)
@@ -320,4 +338,15 @@ def url(n_templates=1_000_000, dups=4, min_len=20, max_len=120, alphabet=40,
         sz = max(1, min(sz, nq - tot))
         sizes.append(sz)
         tot += sz
-    return items, offs, qitems, qoffs, qt * (dups + 1), np.array(sizes, dtype=np.int64)
+    sizes = np.array(sizes, dtype=np.int64)
+    if text:
+        syms = [p[4][0] for p in parts]
+        base, offl = np.uint64(0), [np.zeros(1, dtype=np.uint64)]
+        for p in parts:
+            offl.append(p[4][1][1:] + base)
+            base = base + p[4][1][-1]
+        extra = {"data": (np.concatenate(syms), np.concatenate(offl)),
+                 "queries": _text_of_rows(QA, QL), "gram": 3, "radix": alphabet,
+                 "key": int(key32)}
+        return items, offs, qitems, qoffs, qt * (dups + 1), sizes, extra
+    return items, offs, qitems, qoffs, qt * (dups + 1), sizes

@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="c5: skip the Poisson sweep")
+    ap.add_argument("--no-ext", action="store_true",
+                    help="c5: skip the extensions (text queries, fixed threshold, inserts)")
     ap.add_argument("--cpu-seconds", type=float, default=5.0,
                     help="oracle time per family and thread setting")
     ap.add_argument("--recall-queries", type=int, default=1000)
@@ -736,9 +738,84 @@ def main_mixed(args, torch, fl, configs):
             out["served_poisson"] = poisson_sweep(fl, torch, ws, rates, refs)
     for w in ws:
         w.data_d = None
+    if not args.no_ext:
+        out["extensions"] = extensions(ws[0], torch, fl, configs, args.steps, args.warmup, refs[0])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_mixed(ws, refs, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def extensions(w, torch, fl, configs, steps, warmup, ref):
+    """The query path's extensions on the genome workload: queries given as
+    raw reads (n-gram items extracted on the device), the fixed-threshold
+    query (Algorithm 2), and inserts into a resident index."""
+    import numpy as np
+    out = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n):
+            fn()
+        z.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / n
+
+    tx = w.cfg["text"]
+    txt = (tx["gram"], tx["radix"], tx["key"])
+    sym, off = tx["queries"]
+    text_d = (torch.from_numpy(np.ascontiguousarray(sym).view(np.int8)).cuda(),
+              torch.from_numpy(np.ascontiguousarray(off).view(np.int64)).cuda())
+    ids = torch.empty((w.nq, w.k), dtype=torch.int32, device="cuda")
+    sc = torch.empty((w.nq, w.k), dtype=torch.int32, device="cuda")
+    ms = timed(lambda: w.index.query_text(text_d, txt, w.k, out=(ids, sc)), steps)
+    same = bool(np.array_equal(ids.cpu().numpy().view(np.uint32), ref[0]) and
+                np.array_equal(sc.cpu().numpy().view(np.uint32), ref[1]))
+    out["text_queries"] = {"what": "flinng_query_text: 10,000 raw reads (100 bases) in HBM, "
+                                   "20-gram items extracted on the device, then the query path",
+                           "ms_per_step": round(ms, 4), "qps": round(w.nq / (ms / 1e3), 1),
+                           "identical_to_item_queries": same,
+                           "note": "each call reads two offsets back to size the item buffer"}
+    log(f"text queries: {out['text_queries']}")
+    t = max(1, w.L // 2)
+    cap = 64
+    tids = torch.empty((w.nq, cap), dtype=torch.int32, device="cuda")
+    tcnt = torch.empty((w.nq,), dtype=torch.int32, device="cuda")
+    ms = timed(lambda: w.index.query_threshold(w.q_d, t, cap, out=(tids, tcnt)), steps)
+    cnt = tcnt.cpu().numpy().view(np.uint32)
+    out["threshold_queries"] = {"what": f"flinng_query_threshold at t = {t} of L = {w.L} "
+                                        f"(Algorithm 2), up to {cap} ids per query",
+                                "ms_per_step": round(ms, 4), "qps": round(w.nq / (ms / 1e3), 1),
+                                "mean_answer": round(float(cnt.mean()), 2),
+                                "max_answer": int(cnt.max())}
+    log(f"threshold queries: {out['threshold_queries']}")
+    # inserts: an index of the first 90% of the reads takes the rest in ten batches
+    it, of = w.data
+    N = len(of) - 1
+    n0 = N - N // 10
+    sl = lambda a, b: (it[int(of[a]):int(of[b])], (of[a:b + 1] - of[a]).astype(np.uint64))  # noqa: E731
+    dev = lambda q: (to_dev(torch, q[0]), to_dev(torch, q[1]))  # noqa: E731
+    ix = fl.Index(dev(sl(0, n0)), w.fam, w.K, w.L, w.R, w.B, configs.INDEX_SEED, bucket_bits=w.b)
+    batches = [dev(sl(a, min(N, a + N // 100))) for a in range(n0, N, N // 100)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in batches:
+        ix.insert(b)
+    el = time.perf_counter() - t0
+    n_ins = N - n0
+    out["inserts"] = {"what": f"flinng_index_insert: {len(batches)} batches of {N // 100} reads "
+                              f"(device) into a resident index of {n0} reads",
+                      "points": n_ins, "seconds": round(el, 4),
+                      "points_per_s": round(n_ins / el, 1),
+                      "ms_per_batch": round(el * 1e3 / len(batches), 3),
+                      "list_entries_after": int(ix.info.list_entries)}
+    log(f"inserts: {out['inserts']}")
+    ix.close()
+    return out
 
 
 def main_single(args, torch, fl, configs):

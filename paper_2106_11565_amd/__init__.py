@@ -116,11 +116,17 @@ class Index:
         del keep
         return ids, sc
 
-    def query_threshold(self, q, t, max_per_query, stream=None):
+    def query_threshold(self, q, t, max_per_query, stream=None, out=None):
         """flinng_query_threshold (Algorithm 2 at threshold t), host outputs:
-        (ids [nq, max_per_query] uint32 padded with 0xFFFFFFFF, counts [nq])."""
+        (ids [nq, max_per_query] uint32 padded with 0xFFFFFFFF, counts [nq]);
+        out=(ids, counts) device tensors: the call only enqueues work."""
         inp, keep = make_input(q, self.family)
         nq = inp.count
+        if out is not None:
+            check(lib().flinng_query_threshold(self._h, ctypes.byref(inp), t, max_per_query,
+                                               out[0].data_ptr(), out[1].data_ptr(), 1,
+                                               _stream(stream)))
+            return out
         ids = np.empty((nq, max(max_per_query, 1)), dtype=np.uint32)
         cnt = np.empty(nq, dtype=np.uint32)
         check(lib().flinng_query_threshold(self._h, ctypes.byref(inp), t, max_per_query,

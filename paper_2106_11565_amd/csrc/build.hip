@@ -192,21 +192,44 @@ __global__ void compact_kernel(const uint64_t *__restrict__ keys, const uint32_t
     out[pos[i]] = (CellT)(keys[i] & cmask);
 }
 
-// Bucket offsets without atomics: position i of the sorted keys (i = n for
-// the end) is where every bucket in (bucket(keys[i-1]), bucket(keys[i])]
-// starts, so that position alone writes their offsets, base + the unique
-// entries before it; each offset is written exactly once.
-__global__ void bucket_offsets_kernel(const uint64_t *__restrict__ keys,
-                                      const uint32_t *__restrict__ pos,
-                                      const uint32_t *__restrict__ flag, uint64_t n, int cb,
-                                      uint64_t nbk, uint32_t base, uint32_t *__restrict__ off) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    const uint64_t lo = (i == 0) ? 0 : (keys[i - 1] >> cb) + 1;
-    const uint64_t hi = (i == n) ? nbk : (keys[i] >> cb);
-    if (lo > hi) return;
-    const uint32_t v = base + ((i == n) ? (n ? pos[n - 1] + flag[n - 1] : 0u) : pos[i]);
-    for (uint64_t b = lo; b <= hi; ++b) off[b] = v;
+// Bucket offsets without atomics, as a merge of two sorted sequences: the
+// bucket numbers 0 .. nbk and the buckets of the n sorted keys, where bucket b
+// goes before the keys of buckets >= b.  The offset of bucket b is base plus
+// the unique entries among the keys before it.  Each thread takes OB_ITEMS
+// consecutive items of the merged order: a binary search on its diagonal finds
+// how many keys precede its first item, then it walks its items, consuming a
+// key or writing one offset per step.  The work per thread is bounded however
+// the keys crowd into few buckets (SRP codes of clustered data leave gaps of
+// millions of empty buckets); each offset is written exactly once.
+constexpr uint32_t OB_ITEMS = 128;
+
+__global__ __launch_bounds__(256) void bucket_offsets_kernel(const uint64_t *__restrict__ keys,
+                                                             const uint32_t *__restrict__ pos,
+                                                             const uint32_t *__restrict__ flag,
+                                                             uint64_t n, int cb, uint64_t nbk,
+                                                             uint32_t base,
+                                                             uint32_t *__restrict__ off) {
+    const uint64_t total = nbk + 1 + n;
+    const uint64_t d = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * OB_ITEMS;
+    if (d >= total) return;
+    // the first key index i in [lo, hi) that does not go before bucket d-1-i
+    uint64_t lo = d > nbk + 1 ? d - (nbk + 1) : 0, hi = d < n ? d : n;
+    while (lo < hi) {
+        const uint64_t m = (lo + hi) / 2;
+        if ((keys[m] >> cb) + 1 + m < d) lo = m + 1;  // bucket(keys[m]) < d-1-m
+        else hi = m;
+    }
+    uint64_t i = lo, b = d - lo;
+    const uint32_t last = n ? pos[n - 1] + flag[n - 1] : 0u;
+    const uint64_t end = d + OB_ITEMS < total ? d + OB_ITEMS : total;
+    for (uint64_t e = d; e < end; ++e) {
+        if (i < n && (b > nbk || (keys[i] >> cb) < b)) {
+            ++i;
+        } else {
+            off[b] = base + (i < n ? pos[i] : last);
+            ++b;
+        }
+    }
 }
 
 namespace {
@@ -299,7 +322,8 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
                                        static_cast<uint32_t *>(big) + base);
                 FL_CHECK_LAUNCH();
             }
-            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)((nk + 1 + 255) / 256)),
+            const uint64_t nthr = (nbk + 1 + nk + OB_ITEMS - 1) / OB_ITEMS;
+            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)((nthr + 255) / 256)),
                                dim3(256), 0, s, k, pos.as<uint32_t>(), flag.as<uint32_t>(), nk, cb,
                                nbk, (uint32_t)base, out.offsets + (uint64_t)t * (nbk + 1));
             FL_CHECK_LAUNCH();

@@ -22,6 +22,7 @@
 //      per-table codes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "flinng_internal.h"
@@ -267,125 +268,202 @@ __global__ __launch_bounds__(64 * WM * WN) void srp_mfma_kernel(
 
 // The same products for one bf16 operand plane with both operands staged in
 // LDS: a 256-thread workgroup computes a 128 x 128 tile (four wavefronts of
-// 64 x 64); each 32-wide k slice of the 128 rows and the 128 hyperplanes is
-// loaded once per workgroup (two 16-byte loads per thread and operand),
-// prefetched into registers while the previous slice is multiplied, and
-// double-buffered in LDS with rows padded against bank conflicts.
-// Accumulation is chunked: every LCH consecutive slices accumulate into a
-// fresh partial (MFMA accumulate), and the partials are added in fp32 by the
-// wavefront.  A product then passes through at most LCH*32 roundings inside
-// its chunk (whatever order an instruction sums its 32 products and its
+// 64 x 64) over one range of k.  Each 64-wide k step of the 128 rows and the
+// 128 hyperplanes is loaded once per workgroup (four 16-byte loads per thread
+// and operand), prefetched into registers while the previous step is
+// multiplied, and double-buffered in LDS with rows padded against bank
+// conflicts.  Accumulation is chunked: every 128 consecutive k accumulate into
+// a fresh partial (MFMA accumulate), and the partials are added in fp32 by the
+// wavefront.  A product then passes through at most 128 roundings inside its
+// chunk (whatever order an instruction sums its 32 products and its
 // accumulator in) plus one per chunk, so |v32 - v| <= gamma_m * sum|x_i w_i|
-// with m = min(LCH*32, d) + ceil(d / (LCH*32)) (srp_lds_terms), far below
-// the gamma_d of one long accumulation chain.
+// with m = min(128, d) + ceil(d / 128) (srp_lds_terms), far below the gamma_d
+// of one long accumulation chain.
+//
+// Split k: small batches give fewer tiles than the chip has compute units,
+// and a long k loop is a chain of dependent steps, so the k range is cut into
+// ns pieces of whole chunks, each its own workgroup, writing fp32 partial
+// projections that srp_finish_kernel adds in piece order.  A product then
+// passes through ceil(kpiece / 128) chunk additions and ns - 1 piece
+// additions, which for kpiece a multiple of 128 is at most ceil(d / 128): the
+// bound above holds unchanged.
+//
+// Workgroup order: the hardware hands consecutive workgroup ids to the eight
+// XCDs in turn; ids are renumbered so that the column tiles of one row tile
+// (which read the same rows) run on one XCD, close in time, and share its L2.
 constexpr int LT = 128;          // tile rows and hyperplanes
-constexpr int LK = 32;           // k slice
+constexpr int LK = 64;           // k per pipeline step (two 32-wide MFMA slices)
 constexpr int LROW = LK + 8;     // bf16 per LDS row (16 bytes of padding)
-constexpr int LCH = 4;           // slices per accumulation chunk
+constexpr int LCHK = 128;        // k per accumulation chunk
+constexpr int LPC = LT * LK / 8 / 256;  // 16-byte pieces per thread and operand
 
 // Roundings a product passes through in srp_mfma_lds_kernel (see above).
 inline uint32_t srp_lds_terms(uint32_t dpad) {
-    const uint32_t chunk = LCH * LK;
-    return (dpad < chunk ? dpad : chunk) + (dpad + chunk - 1) / chunk;
+    return (dpad < (uint32_t)LCHK ? dpad : (uint32_t)LCHK) + (dpad + LCHK - 1) / LCHK;
+}
+
+// How the LDS kernel covers n rows: tiles of 128 x 128 and k pieces.
+struct SrpSplit {
+    uint32_t nct, nrt, ns, kpiece;
+};
+
+static SrpSplit srp_split(uint32_t H, uint64_t n, uint32_t dpad) {
+    SrpSplit sp;
+    sp.nct = (H + LT - 1) / LT;
+    sp.nrt = (uint32_t)((n + LT - 1) / LT);
+    const uint64_t tiles = (uint64_t)sp.nct * sp.nrt;
+    const uint32_t nch = (dpad + LCHK - 1) / LCHK;
+    // Two workgroups fit on each of the 256 compute units.  Estimated time:
+    // (rounds of resident workgroups) x (chunks per piece) x the time of one
+    // chunk at full load (about 2.8 us measured), plus writing and reading
+    // the fp32 partials of more than one piece (at about 5000 bytes per ns).
+    constexpr uint64_t SLOTS = 512;
+    constexpr double CHUNK_NS = 2800.0, NS_PER_BYTE = 1.0 / 5000.0;
+    uint32_t best = 1;
+    double best_cost = 0.0;
+    for (uint32_t ns = 1; ns <= nch; ++ns) {
+        const uint32_t cps = (nch + ns - 1) / ns;
+        if (ns > 1 && (nch + cps - 1) / cps < ns) continue;  // same split as fewer pieces
+        const uint64_t rounds = (tiles * ns + SLOTS - 1) / SLOTS;
+        double cost = (double)rounds * cps * CHUNK_NS;
+        if (ns > 1) cost += NS_PER_BYTE * 8.0 * ns * (double)n * H;
+        if (ns == 1 || cost < best_cost) {
+            best_cost = cost;
+            best = ns;
+        }
+    }
+    const uint32_t cps = (nch + best - 1) / best;
+    sp.kpiece = cps * LCHK;
+    sp.ns = (nch + cps - 1) / cps;
+    return sp;
 }
 
 __global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
     const uint16_t *__restrict__ planes, uint32_t ld, const uint16_t *__restrict__ w,
     uint32_t dpad, const float *__restrict__ nx, const float *__restrict__ nw, uint64_t n,
-    uint32_t H, uint32_t Hw, float gamma, float tau_abs, uint16_t *__restrict__ bits16,
+    uint32_t H, uint32_t Hw, float gamma, float tau_abs, uint32_t nct, uint32_t nrt,
+    uint32_t kpiece, float *__restrict__ part, uint16_t *__restrict__ bits16,
     uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag,
     float *__restrict__ proj) {
     __shared__ __align__(16) uint16_t sa[2][LT * LROW];
     __shared__ __align__(16) uint16_t sb[2][LT * LROW];
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int wm = wave / 2, wn = wave % 2;
-    const uint64_t tr0 = (uint64_t)blockIdx.y * LT;
-    const uint32_t tc0 = blockIdx.x * LT;
+    uint32_t lid = blockIdx.x;
+    {
+        const uint32_t per = gridDim.x / 8;
+        if (lid < per * 8) lid = (lid % 8) * per + lid / 8;
+    }
+    const uint32_t ct = lid % nct, rt = (lid / nct) % nrt, ks = lid / (nct * nrt);
+    const uint64_t tr0 = (uint64_t)rt * LT;
+    const uint32_t tc0 = ct * LT;
+    const uint32_t kbeg = ks * kpiece;
+    const uint32_t kend = (kbeg + kpiece < dpad) ? kbeg + kpiece : dpad;
 
-    // this thread's two 16-byte pieces of each operand slice: piece u covers
-    // tile row u / 4, k offset 8 * (u % 4), for u = tid and tid + 256 (named
-    // registers and no branches, so the prefetch stays in registers)
-    const int u0 = tid, u1 = tid + 256;
-    const int rr0 = u0 / 4, rr1 = u1 / 4, kk0 = 8 * (u0 % 4), kk1 = 8 * (u1 % 4);
-    const uint64_t r0 = (tr0 + rr0 < n) ? tr0 + rr0 : n - 1;
-    const uint64_t r1 = (tr0 + rr1 < n) ? tr0 + rr1 : n - 1;
-    const uint32_t c0 = (tc0 + rr0 < H) ? tc0 + rr0 : H - 1;
-    const uint32_t c1 = (tc0 + rr1 < H) ? tc0 + rr1 : H - 1;
-    const uint16_t *ga0 = planes + r0 * ld + kk0;
-    const uint16_t *ga1 = planes + r1 * ld + kk1;
-    const uint16_t *gb0 = w + (uint64_t)c0 * dpad + kk0;
-    const uint16_t *gb1 = w + (uint64_t)c1 * dpad + kk1;
-    const int so0 = rr0 * LROW + kk0, so1 = rr1 * LROW + kk1;
-
-    uint4 ra0 = *reinterpret_cast<const uint4 *>(ga0);
-    uint4 ra1 = *reinterpret_cast<const uint4 *>(ga1);
-    uint4 rb0 = *reinterpret_cast<const uint4 *>(gb0);
-    uint4 rb1 = *reinterpret_cast<const uint4 *>(gb1);
-    *reinterpret_cast<uint4 *>(&sa[0][so0]) = ra0;
-    *reinterpret_cast<uint4 *>(&sa[0][so1]) = ra1;
-    *reinterpret_cast<uint4 *>(&sb[0][so0]) = rb0;
-    *reinterpret_cast<uint4 *>(&sb[0][so1]) = rb1;
+    // this thread's pieces of each operand step: piece u = tid + 256 j covers
+    // tile row u / 8 (= tid / 8 + 32 j), k offset 8 * (tid % 8); pieces at or
+    // past kend (the last step of an odd number of 32-wide slices) are zero
+    const int kk = 8 * (tid % 8), rr = tid / 8;
+    const uint16_t *ga[LPC];
+    const uint16_t *gb[LPC];
+#pragma unroll
+    for (int j = 0; j < LPC; ++j) {
+        const uint64_t r = (tr0 + rr + 32 * j < n) ? tr0 + rr + 32 * j : n - 1;
+        const uint32_t c = (tc0 + rr + 32 * j < H) ? tc0 + rr + 32 * j : H - 1;
+        ga[j] = planes + r * ld + kk;
+        gb[j] = w + (uint64_t)c * dpad + kk;
+    }
+    const int so = rr * LROW + kk;
+    uint4 ra[LPC], rb[LPC];
+    auto fetch = [&](uint32_t k) {
+        const bool in = k + kk < kend;
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) {
+            ra[j] = in ? *reinterpret_cast<const uint4 *>(ga[j] + k) : uint4{0u, 0u, 0u, 0u};
+            rb[j] = in ? *reinterpret_cast<const uint4 *>(gb[j] + k) : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) {
+            *reinterpret_cast<uint4 *>(&sa[buf][so + 32 * j * LROW]) = ra[j];
+            *reinterpret_cast<uint4 *>(&sb[buf][so + 32 * j * LROW]) = rb[j];
+        }
+    };
+    fetch(kbeg);
+    stage(0);
     __syncthreads();
 
-    f32x4 acc[4][4], part[4][4];
+    f32x4 acc[4][4], prt[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-            part[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     const int lr = lane % 16, lk = (lane / 16) * 8;
 
-    for (uint32_t k0 = 0; k0 < dpad; k0 += LK) {
-        const uint32_t step = k0 / LK;
-        const int cur = step & 1;
-        // next slice (the last iteration reloads its own slice into the
-        // buffer nobody reads any more)
-        const uint32_t kn = (k0 + LK < dpad) ? k0 + LK : k0;
-        ra0 = *reinterpret_cast<const uint4 *>(ga0 + kn);
-        ra1 = *reinterpret_cast<const uint4 *>(ga1 + kn);
-        rb0 = *reinterpret_cast<const uint4 *>(gb0 + kn);
-        rb1 = *reinterpret_cast<const uint4 *>(gb1 + kn);
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += LK) {
+        const int cur = ((k0 - kbeg) / LK) & 1;
+        const bool more = k0 + LK < kend;
+        if (more) fetch(k0 + LK);
         const uint16_t *ca = sa[cur];
         const uint16_t *cb = sb[cur];
-        bf16x8 fa[4], fb[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-            fa[a] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const uint4 *>(&ca[(wm * 64 + 16 * a + lr) * LROW + lk]));
+        for (int hs = 0; hs < LK / 32; ++hs) {
+            bf16x8 fa[4], fb[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            fb[b] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const uint4 *>(&cb[(wn * 64 + 16 * b + lr) * LROW + lk]));
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
+                fa[a] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(
+                                &ca[(wm * 64 + 16 * a + lr) * LROW + 32 * hs + lk]));
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                part[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], part[a][b], 0, 0, 0);
-        if ((step + 1) % LCH == 0 || k0 + LK >= dpad) {
+                fb[b] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(
+                                &cb[(wn * 64 + 16 * b + lr) * LROW + 32 * hs + lk]));
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    prt[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], prt[a][b], 0, 0, 0);
+        }
+        if ((k0 + LK - kbeg) % LCHK == 0 || !more) {
             // close the chunk: one fp32 addition per output
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[a][b][i] += part[a][b][i];
-                    part[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    for (int i = 0; i < 4; ++i) acc[a][b][i] += prt[a][b][i];
+                    prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
         }
-        uint16_t *na = sa[cur ^ 1];
-        uint16_t *nb = sb[cur ^ 1];
-        *reinterpret_cast<uint4 *>(&na[so0]) = ra0;
-        *reinterpret_cast<uint4 *>(&na[so1]) = ra1;
-        *reinterpret_cast<uint4 *>(&nb[so0]) = rb0;
-        *reinterpret_cast<uint4 *>(&nb[so1]) = rb1;
+        if (more) stage(cur ^ 1);
         __syncthreads();
     }
 
-    // Epilogue: trusted sign bits and flags, 16 columns per ballot group.
     const uint64_t row0 = tr0 + (uint64_t)wm * 64;
     const uint32_t col0 = tc0 + wn * 64;
+    if (part) {
+        // one k piece of several: its partial projections
+        float *pp = part + (uint64_t)ks * n * H;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t col = col0 + 16 * b + lr;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
+                    if (row < n && col < H) pp[row * H + col] = acc[a][b][i];
+                }
+        }
+        return;
+    }
+
+    // Epilogue: trusted sign bits and flags, 16 columns per ballot group.
     unsigned long long flagged = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -420,27 +498,101 @@ __global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
     if ((lane % 16) == 0 && flagged) atomicAdd(nflag, flagged);
 }
 
+// Sum of the k pieces' partial projections, in piece order, then the same
+// certificate as the single-piece epilogue.  A thread takes one hyperplane of
+// RB consecutive rows; the 16 lanes 16j .. 16j+15 of a wavefront hold one
+// group of 16 hyperplanes (reads of consecutive hyperplanes are coalesced),
+// and each row's sign and flag words of the group come from two ballots.
+// Loads carry no branches (rows and hyperplanes are clamped into range, the
+// clamped values unused), so that they are in flight together.
+template <int RB>
+__global__ __launch_bounds__(256) void srp_finish_kernel(
+    const float *__restrict__ part, uint32_t ns, uint64_t n, uint64_t r0, uint32_t nr,
+    uint32_t H, uint32_t Hw, const float *__restrict__ nx, const float *__restrict__ nw,
+    float gamma, float tau_abs, uint16_t *__restrict__ bits16, uint16_t *__restrict__ flags16,
+    unsigned long long *__restrict__ nflag, float *__restrict__ proj) {
+    // rows r0 .. r0 + nr - 1; the thread count is below 2^31, so the
+    // indexing is 32-bit
+    const uint32_t G = (H + 15) / 16;
+    const int lane = threadIdx.x % 64;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t grp = t / 16;
+    const uint32_t rbk = grp / G;
+    const uint32_t g = grp - rbk * G, col = 16 * g + t % 16;
+    const uint32_t rl0 = rbk * RB;
+    const uint64_t pstride = n * H;
+    const uint32_t cc = col < H ? col : H - 1;
+    uint64_t ro[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) ro[r] = (r0 + (rl0 + r < nr ? rl0 + r : nr - 1)) * H + cc;
+    float v[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) v[r] = 0.f;
+    if (rl0 < nr) {
+        if constexpr (RB == 1) {
+#pragma unroll 8
+            for (uint32_t s = 0; s < ns; ++s) v[0] += part[(uint64_t)s * pstride + ro[0]];
+        } else {
+            for (uint32_t s = 0; s < ns; ++s) {
+                const float *ps = part + (uint64_t)s * pstride;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) v[r] += ps[ro[r]];
+            }
+        }
+    }
+    unsigned long long nf = 0;
+    const float wn_ = nw[cc];
+    float xn[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) xn[r] = nx[r0 + (rl0 + r < nr ? rl0 + r : nr - 1)];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const uint32_t rl = rl0 + r;
+        const uint64_t row = r0 + rl;
+        bool bit = false, flg = false;
+        if (rl < nr && col < H) {
+            if (proj) proj[row * H + col] = v[r];
+            const float tau = gamma * xn[r] * wn_ + tau_abs;
+            const bool ok = fabsf(v[r]) > tau;
+            bit = ok && (v[r] > 0.f);
+            flg = !ok;
+        }
+        const unsigned long long mb = __ballot(bit);
+        const unsigned long long mf = __ballot(flg);
+        if (lane % 16 == 0 && rl < nr) {
+            const uint64_t o = row * (2 * (uint64_t)Hw) + g;
+            bits16[o] = (uint16_t)(mb >> lane);
+            flags16[o] = (uint16_t)(mf >> lane);
+        }
+        nf += (unsigned long long)__popcll(mf);
+    }
+    if (lane == 0 && nf) atomicAdd(nflag, nf);
+}
+
 // ---------------------------------------------------------------------------
 // Exact sign of sum_i x_i * w_i when FP64 cannot certify it.  Every product
 // is an exact double m * 2^e with |m| < 2^31 and e >= -151 (x: fp32/bf16,
 // w: quarter-integer); products are added into 32-bit digits of a signed
-// fixed-point number spanning 2^-160 .. 2^224 (int64 digits absorb carries
-// for up to 2^30 terms), then carries are propagated and the sign read from
-// the top.  Runs on one lane; reached only for near-exact cancellations.
-__device__ int exact_sign_fixed(const void *xin, bool f32, uint64_t row, uint32_t d,
-                                const uint16_t *__restrict__ wh) {
+// fixed-point number spanning 2^-160 .. 2^224, then carries are propagated
+// and the sign read from the top.  The whole wavefront calls it: lane l adds
+// the products i = l, l + 64, ... into its own int64 digits, which are then
+// summed across the wavefront (no overflow for up to 2^30 terms in all), so
+// every lane returns the same sign.
+__device__ int exact_sign_wave(const void *xin, bool f32, uint64_t row, uint32_t d,
+                               const uint16_t *__restrict__ wh) {
     constexpr int NLIMB = 12;
     constexpr int BASE = -160;
     long long limb[NLIMB];
+#pragma unroll
     for (int j = 0; j < NLIMB; ++j) limb[j] = 0;
-    for (uint32_t i = 0; i < d; ++i) {
-        double xv = f32 ? (double)static_cast<const float *>(xin)[row * d + i]
-                        : (double)bf16_to_f32(static_cast<const uint16_t *>(xin)[row * d + i]);
-        double p = xv * (double)bf16_to_f32(wh[i]);
+    for (uint32_t i = threadIdx.x % 64; i < d; i += 64) {
+        const double xv = f32 ? (double)static_cast<const float *>(xin)[row * d + i]
+                              : (double)bf16_to_f32(static_cast<const uint16_t *>(xin)[row * d + i]);
+        const double p = xv * (double)bf16_to_f32(wh[i]);
         if (p == 0.0) continue;
-        unsigned long long bits = (unsigned long long)__double_as_longlong(p);
-        bool neg = bits >> 63;
-        int ex = (int)((bits >> 52) & 0x7FF);
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(p);
+        const bool neg = bits >> 63;
+        const int ex = (int)((bits >> 52) & 0x7FF);
         unsigned long long m = bits & ((1ull << 52) - 1);
         int pos;
         if (ex == 0) {
@@ -449,31 +601,40 @@ __device__ int exact_sign_fixed(const void *xin, bool f32, uint64_t row, uint32_
             m |= (1ull << 52);
             pos = ex - 1075;
         }
-        while ((m & 1ull) == 0) {
-            m >>= 1;
-            ++pos;
-        }
-        int sh = pos - BASE;  // >= 9 for the supported inputs
-        int j = sh / 32, o = sh % 32;
+        const int tz = __builtin_ctzll(m);  // m != 0: p is not zero
+        m >>= tz;
+        pos += tz;
+        const int sh = pos - BASE;  // >= 9 for the supported inputs
+        const int j = sh / 32, o = sh % 32;
         // m < 2^31 after stripping: (m << o) < 2^63
-        unsigned long long v = m << o;
+        const unsigned long long v = m << o;
         long long lo = (long long)(v & 0xFFFFFFFFull), hi = (long long)(v >> 32);
         if (neg) {
             lo = -lo;
             hi = -hi;
         }
-        limb[j] += lo;
-        if (j + 1 < NLIMB) limb[j + 1] += hi;
+        // registers, not a dynamically indexed array
+#pragma unroll
+        for (int q = 0; q < NLIMB; ++q) {
+            limb[q] += (q == j) ? lo : 0ll;
+            limb[q] += (q == j + 1) ? hi : 0ll;
+        }
     }
+#pragma unroll
+    for (int q = 0; q < NLIMB; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) limb[q] += __shfl_xor(limb[q], o, 64);
+#pragma unroll
     for (int j = 0; j < NLIMB - 1; ++j) {
-        long long c = limb[j] >> 32;  // arithmetic shift: floor division
+        const long long c = limb[j] >> 32;  // arithmetic shift: floor division
         limb[j] -= c * (1ll << 32);
         limb[j + 1] += c;
     }
     if (limb[NLIMB - 1] != 0) return limb[NLIMB - 1] > 0 ? 1 : -1;
-    for (int j = NLIMB - 2; j >= 0; --j)
-        if (limb[j] != 0) return 1;
-    return 0;
+    int any = 0;
+#pragma unroll
+    for (int j = NLIMB - 2; j >= 0; --j) any |= limb[j] != 0;
+    return any;
 }
 
 // Recheck + pack: one wavefront per row.  Bits of the row are staged in LDS
@@ -517,15 +678,13 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_kernel(
                 v = wave_sum_f64(v);
                 a = wave_sum_f64(a);
                 int sgn;
-                if (fabs(v) > 2.0 * (double)d * 0x1p-53 * a) {
+                // the butterfly sums are bit-identical in every lane; take
+                // lane 0's verdict so the branch is uniform by construction
+                if (__builtin_amdgcn_readfirstlane(fabs(v) > 2.0 * (double)d * 0x1p-53 * a ? 1 : 0)) {
                     sgn = v > 0.0 ? 1 : -1;
                 } else {
-                    sgn = 0;
-                    if (lane == 0) {
-                        sgn = exact_sign_fixed(xin, f32 != 0, row, d, wh);
-                        atomicAdd(nexact, 1ull);
-                    }
-                    sgn = __shfl(sgn, 0, 64);
+                    sgn = exact_sign_wave(xin, f32 != 0, row, d, wh);
+                    if (lane == 0) atomicAdd(nexact, 1ull);
                 }
                 if (lane == 0) {
                     uint32_t m = 1u << bit;
@@ -552,9 +711,10 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_kernel(
 
 // Recheck + pack for bf16 rows read in place (d a multiple of 32, rows
 // 16-byte aligned).  One wavefront per row: its flagged hyperplanes are
-// listed in LDS, then recomputed four at a time, 16 lanes each, with 16-byte
-// loads of 8 bf16 values of the row and of the hyperplane and FP64 partial
-// sums reduced within the 16 lanes.  Same certificate and exact fallback as
+// listed in LDS, then recomputed one at a time across the wavefront, with
+// 16-byte loads of 8 bf16 values of the row and of the hyperplane and FP64
+// partial sums reduced across the lanes (one round of memory latency per
+// flagged projection).  Same certificate and exact fallback as
 // srp_recheck_pack_kernel.
 __global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
     const uint16_t *__restrict__ x, uint64_t n, uint32_t d, const uint16_t *__restrict__ w,
@@ -586,26 +746,24 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
         while (fw) {
             const uint32_t b = (uint32_t)(__ffs(fw) - 1);
             fw &= fw - 1;
-            const uint32_t h = j * 32 + b;
-            if (h < H) fl[pos] = (uint16_t)h;
-            ++pos;
+            fl[pos++] = (uint16_t)(j * 32 + b);
         }
         nf += (uint32_t)__shfl((int)inc, 63, 64);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int g = lane >> 4, sl = lane & 15;
+    // each flagged projection is recomputed by the whole wavefront: lane l
+    // takes the 8-value pieces l, l + 64, ... of the row and the hyperplane,
+    // all loads in flight at once
     const uint16_t *xr = x + row * d;
-    for (uint32_t p0 = 0; p0 < nf; p0 += 4) {
-        const uint32_t p = p0 + g;
-        const bool act = p < nf;
-        const uint32_t h = fl[act ? p : nf - 1];
+    for (uint32_t p = 0; p < nf; ++p) {
+        const uint32_t h = fl[p];
         if (h >= H) continue;  // never: flags past H are zero
         const uint16_t *wh = w + (uint64_t)h * d;
         double v = 0.0, a = 0.0;
-#pragma unroll 4
-        for (uint32_t i = 8 * sl; i < d; i += 128) {
+#pragma unroll 8
+        for (uint32_t i = 8 * lane; i < d; i += 512) {
             const uint4 xv = *reinterpret_cast<const uint4 *>(xr + i);
             const uint4 wv = *reinterpret_cast<const uint4 *>(wh + i);
             const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
@@ -623,19 +781,18 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
                 a += fabs(p1_);
             }
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            v += __shfl_xor(v, o, 64);
-            a += __shfl_xor(a, o, 64);
+        v = wave_sum_f64(v);
+        a = wave_sum_f64(a);
+        int sgn;
+        // the butterfly sums are bit-identical in every lane; lane 0's
+        // verdict keeps the branch uniform by construction
+        if (__builtin_amdgcn_readfirstlane(fabs(v) > 2.0 * (double)d * 0x1p-53 * a ? 1 : 0)) {
+            sgn = v > 0.0 ? 1 : -1;
+        } else {
+            sgn = exact_sign_wave(x, false, row, d, wh);
+            if (lane == 0) atomicAdd(nexact, 1ull);
         }
-        int sgn = 0;
-        if (act && sl == 0) {
-            if (fabs(v) > 2.0 * (double)d * 0x1p-53 * a) {
-                sgn = v > 0.0 ? 1 : -1;
-            } else {
-                sgn = exact_sign_fixed(x, false, row, d, wh);
-                atomicAdd(nexact, 1ull);
-            }
+        if (lane == 0) {
             const uint32_t m = 1u << (h & 31);
             if (sgn > 0)
                 atomicOr(&rb[h >> 5], m);
@@ -681,8 +838,13 @@ size_t srp_scratch_bytes(const Index &ix, uint64_t n, const void *xdev) {
     const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
     const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
     const bool planes = !(xdev && srp_inplace(ix, xdev));
+    size_t partial = 0;
+    if (nsplit == 1) {
+        const SrpSplit sp = srp_split(ix.p.K * ix.p.L, n, ix.dpad);
+        if (sp.ns > 1) partial = Arena::round((size_t)sp.ns * n * ix.p.K * ix.p.L * 4);
+    }
     return (planes ? Arena::round((size_t)nsplit * n * ix.dpad * 2) : 0) + Arena::round(n * 4) +
-           2 * Arena::round(n * Hw * 4) + Arena::round(16);
+           2 * Arena::round(n * Hw * 4) + Arena::round(16) + partial;
 }
 
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
@@ -711,6 +873,15 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     uint32_t *bits = sc.get<uint32_t>(n * Hw * 4);
     uint32_t *flags = sc.get<uint32_t>(n * Hw * 4);
     unsigned long long *ctr = sc.get<unsigned long long>(16);
+    // bf16 rows: the LDS kernel, with k split into pieces for small batches
+    SrpSplit sp{};
+    float *part = nullptr;
+    if (nsplit == 1) {
+        sp = srp_split(H, n, dpad);
+        if ((uint64_t)sp.nct * sp.nrt * sp.ns > 0x7FFFFFFFull)
+            fail(FLINNG_EINVAL, "SRP batch too large for one launch");
+        if (sp.ns > 1) part = sc.get<float>((size_t)sp.ns * n * H * 4);
+    }
     {
         dim3 grid((unsigned)((n + 3) / 4));
         if (f32)
@@ -739,12 +910,35 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
                            pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
                            reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
                            nflag, proj_dev);
-    else
-        hipLaunchKernelGGL(srp_mfma_lds_kernel,
-                           dim3((H + LT - 1) / LT, (unsigned)((n + LT - 1) / LT)), dim3(256), 0, s,
-                           pl, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
-                           reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
-                           nflag, proj_dev);
+    else {
+        hipLaunchKernelGGL(srp_mfma_lds_kernel, dim3(sp.nct * sp.nrt * sp.ns), dim3(256), 0, s, pl,
+                           ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs, sp.nct,
+                           sp.nrt, sp.kpiece, part, reinterpret_cast<uint16_t *>(bits),
+                           reinterpret_cast<uint16_t *>(flags), nflag, part ? nullptr : proj_dev);
+        if (part) {
+            FL_CHECK_LAUNCH();
+            // rows per thread: RB * ns loads in flight
+            const int rb = sp.ns >= 8 ? 1 : 4;
+            const uint64_t per_rb = (uint64_t)((H + 15) / 16) * 16;
+            const uint64_t rows_max = ((1ull << 30) / per_rb) * rb;
+            uint16_t *b16 = reinterpret_cast<uint16_t *>(bits);
+            uint16_t *f16 = reinterpret_cast<uint16_t *>(flags);
+            for (uint64_t r0 = 0; r0 < n; r0 += rows_max) {
+                const uint32_t nr = (uint32_t)std::min<uint64_t>(rows_max, n - r0);
+                const uint64_t nt = (nr + rb - 1) / rb * per_rb;
+                const dim3 g((unsigned)((nt + 255) / 256));
+                if (rb == 1)
+                    hipLaunchKernelGGL(srp_finish_kernel<1>, g, dim3(256), 0, s, part, sp.ns, n, r0,
+                                       nr, H, Hw, nx, ix.hypnorm, gamma, tau_abs, b16, f16, nflag,
+                                       proj_dev);
+                else
+                    hipLaunchKernelGGL(srp_finish_kernel<4>, g, dim3(256), 0, s, part, sp.ns, n, r0,
+                                       nr, H, Hw, nx, ix.hypnorm, gamma, tau_abs, b16, f16, nflag,
+                                       proj_dev);
+                FL_CHECK_LAUNCH();
+            }
+        }
+    }
     FL_CHECK_LAUNCH();
     if (inplace)
         hipLaunchKernelGGL(srp_recheck_pack_vec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),

@@ -404,7 +404,7 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
             const uint32_t ci = cpc == 1 ? ic : ic / cpc;
             const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
             const uint32_t j0 = (ic - ci * cpc) * 256;
-            const uint32_t sz = gsz[bb];
+            const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
             const uint32_t j = j0 + 4 * lane;
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
             if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
@@ -838,7 +838,9 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 misc[M_MEMB] = 0;
             }
             __syncthreads();
-            const uint32_t level = misc[M_LEVEL], rep = misc[M_REP];
+            // uniform across the workgroup: kept in scalar registers
+            const uint32_t level = __builtin_amdgcn_readfirstlane(misc[M_LEVEL]);
+            const uint32_t rep = __builtin_amdgcn_readfirstlane(misc[M_REP]);
             const bool keep = misc[M_KEEPALL] != 0;
             const uint32_t *memr = A.mem + rep * rstride;
             const uint16_t *cmgr = A.cmg + rep * rstride * RP;

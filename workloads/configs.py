@@ -57,8 +57,9 @@ def make(name, scale=1.0, nq=None):
         return cfg, X, Q, qb
     if name == "c2":
         nb = max(1, int(cfg["n_base"] * scale))
-        it, of, qit, qof, qb = synth.genome(n_base=nb, nq=nq)
+        it, of, qit, qof, qb, text = synth.genome(n_base=nb, nq=nq, text=True)
         cfg["N"] = 2 * nb
+        cfg["text"] = text   # the reads as symbol sequences, and their n-gram item map
         return cfg, (it, of), (qit, qof), qb
     if name == "c3":
         N = max(2, int(cfg["N"] * scale))

@@ -236,11 +236,17 @@ def stages(w, torch, fl, steps, persistent, out):
     torch.cuda.synchronize()
     st = [int(v) for v in stats.cpu().tolist()]
     # algorithmic bytes of one decode launch: codes (L*4) and bucket offset
-    # pairs (L*8) per query, every list entry read, each member id read by the
-    # final decode pass (4 B), the R group ids of each candidate it gathers
-    # (2R B), and k ids + scores out
+    # pairs (L*8) per query, every list entry read, and for each member of
+    # the final pass's cells its id and its R group ids (4 + 2R B: the
+    # decode minimum of the straightforward walk), and k ids + scores out.
+    # The kernel itself reads less: a 4-byte filter word per member and the
+    # id and row only of the members that pass it (touched_bytes).
     cb = w.index.info.cell_id_bytes
-    alg = w.nq * w.L * 12 + st[0] * cb + st[2] * 4 + st[4] * 2 * w.R + w.nq * w.k * 8
+    Rp = 1
+    while Rp < w.R:
+        Rp *= 2
+    alg = w.nq * w.L * 12 + st[0] * cb + st[2] * (4 + 2 * w.R) + w.nq * w.k * 8
+    touched = w.nq * w.L * 12 + st[0] * cb + st[2] * 4 + st[4] * (4 + 2 * Rp) + w.nq * w.k * 8
     ach = alg / (decode_ms / 1e3) / 1e9
     roof = {"kernel": "query_kernel (count + threshold + decode)", "workload": w.name,
             "K": w.K, "L": w.L, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -248,8 +254,8 @@ def stages(w, torch, fl, steps, persistent, out):
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled; "
                             "read from the committed counter summary for this kernel source)",
             "alg_bytes_per_launch": int(alg), "launch_ms": round(decode_ms, 4),
-            "list_entries": st[0], "member_ids_all_passes": st[1], "member_ids_final": st[2],
-            "passes": st[3], "group_rows_gathered": st[4]}
+            "list_entries": st[0], "members_all_passes": st[1], "members_final": st[2],
+            "passes": st[3], "rows_gathered_final": st[4], "touched_bytes_per_launch": int(touched)}
     out = {"hash_ms": hash_ms, "decode_ms": decode_ms, "query_roofline": roof}
     if w.dense:
         # the hash stage (norms, bf16 MFMA projection, FP64 recheck, pack)

@@ -182,9 +182,11 @@ int flinng_query_text(const flinng_index *idx, const flinng_text *q, uint32_t k,
  *          outside that range matches no bucket, so its table adds nothing.
  *  ids, scores  (device) nq*k uint32 as in flinng_query (scores may be NULL).
  *  stats   (device, optional) 5 uint64 that the launch adds to: reverse-index
- *          list entries read, cell member ids read over all decode passes,
- *          member ids read in the final passes, decode passes, and candidate
- *          group rows gathered in the final passes.  The caller zeroes them.
+ *          list entries read, cell members walked over all decode passes,
+ *          cell members walked in the final passes (each costs a 4-byte read:
+ *          its id, or its filter word where the pass filters), decode passes,
+ *          and candidate group rows gathered in the final passes (every
+ *          walked member, or the filter's survivors).  The caller zeroes them.
  * Returns once the work is enqueued on `stream`.
  */
 int flinng_query_codes(const flinng_index *idx, const uint32_t *codes, uint64_t nq,

@@ -112,6 +112,7 @@ static void free_index(Index *ix) {
     if (ix->grp) (void)hipFree(ix->grp);
     if (ix->mem) (void)hipFree(ix->mem);
     if (ix->cmg) (void)hipFree(ix->cmg);
+    if (ix->cfl) (void)hipFree(ix->cfl);
     if (ix->hyp) (void)hipFree(ix->hyp);
     if (ix->hypnorm) (void)hipFree(ix->hypnorm);
     if (ix->gsize) (void)hipFree(ix->gsize);
@@ -171,6 +172,7 @@ static void build_impl(const flinng_params *p, const flinng_input *data, hipStre
         ix->mstride = (uint32_t)((gmax + 3) & ~3ull);
         ix->mem = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
         ix->cmg = dmalloc<uint16_t>((uint64_t)p->R * p->B * ix->mstride * ix->Rp, bytes);
+        ix->cfl = dmalloc<uint32_t>((uint64_t)p->R * p->B * ix->mstride, bytes);
         if (dense) {
             ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
             ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);

@@ -99,6 +99,31 @@ __global__ void cell_groups_kernel(const uint32_t *__restrict__ mem, const uint1
         cmg[sl * Rp + r] = (x == 0xFFFFFFFFu) ? (uint16_t)0 : grp[(uint64_t)x * Rp + r];
 }
 
+// cfl[r][b][j] = the groups, in repetitions r+1 and r+2 (mod R), of the
+// member in slot j of cell (r, b): low and high 16 bits (zero for padding
+// slots).  One launch per repetition r.
+__global__ void filter_groups_kernel(const uint32_t *__restrict__ mem_r,
+                                     const uint16_t *__restrict__ grp, uint64_t nslots, uint32_t Rp,
+                                     uint32_t r1, uint32_t r2, uint32_t *__restrict__ cfl_r) {
+    const uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslots) return;
+    const uint32_t x = mem_r[sl];
+    cfl_r[sl] = (x == 0xFFFFFFFFu)
+                    ? 0u
+                    : (uint32_t)grp[(uint64_t)x * Rp + r1] | ((uint32_t)grp[(uint64_t)x * Rp + r2] << 16);
+}
+
+void build_filter(const Index &ix, const uint32_t *mem, const uint16_t *grp, uint32_t mstride,
+                  uint32_t *cfl, hipStream_t s) {
+    const uint32_t R = ix.p.R, B = ix.p.B;
+    const uint64_t per = (uint64_t)B * mstride;
+    for (uint32_t r = 0; r < R; ++r) {
+        hipLaunchKernelGGL(filter_groups_kernel, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,
+                           mem + r * per, grp, per, ix.Rp, (r + 1) % R, (r + 2) % R, cfl + r * per);
+        FL_CHECK_LAUNCH();
+    }
+}
+
 void build_groups(Index &ix, hipStream_t s) {
     const uint64_t N = ix.N;
     const uint32_t R = ix.p.R, B = ix.p.B;
@@ -133,6 +158,7 @@ void build_groups(Index &ix, hipStream_t s) {
     hipLaunchKernelGGL(cell_groups_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s,
                        ix.mem, ix.grp, nslots, ix.Rp, ix.cmg);
     FL_CHECK_LAUNCH();
+    build_filter(ix, ix.mem, ix.grp, ix.mstride, ix.cfl, s);
     // cell sizes (Algorithm 1's balanced design), on the device and the host
     ix.gsize_host.assign((size_t)R * B, 0);
     for (uint32_t r = 0; r < R; ++r)
@@ -442,7 +468,7 @@ void insert_points(Index &ix, const uint32_t *codes, uint64_t n, hipStream_t s) 
     auto dfree = [](void *p) { if (p) (void)hipFree(p); };
     // arrays of the new version (freed on failure)
     uint16_t *grp1 = nullptr, *cmg1 = nullptr;
-    uint32_t *mem1 = nullptr, *gsize1 = nullptr;
+    uint32_t *mem1 = nullptr, *gsize1 = nullptr, *cfl1 = nullptr;
     Lists lists;
     try {
         // 1. group rows of the arrivals (grp is not read by queries; a larger
@@ -519,6 +545,8 @@ void insert_points(Index &ix, const uint32_t *codes, uint64_t n, hipStream_t s) 
                                cmg1 + (uint64_t)r * B * ms1 * Rp);
             FL_CHECK_LAUNCH();
         }
+        FL_HIP(hipMalloc(&cfl1, ncells * ms1 * 4));
+        build_filter(ix, mem1, grp, ms1, cfl1, s);
         FL_HIP(hipMalloc(&gsize1, ncells * 4));
         hipLaunchKernelGGL(add_u32_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s,
                            ix.gsize, cnt.as<uint32_t>(), ncells, gsize1);
@@ -529,13 +557,15 @@ void insert_points(Index &ix, const uint32_t *codes, uint64_t n, hipStream_t s) 
         // 5. swap the new version in while no query is being enqueued, and
         //    free the old one once the device has finished all work using it
         std::unique_lock<std::shared_mutex> lk(ix.rw);
-        void *old[6] = {ix.offsets, ix.cells, ix.mem, ix.cmg, ix.gsize, grp1 ? ix.grp : nullptr};
+        void *old[7] = {ix.offsets, ix.cells, ix.mem, ix.cmg, ix.cfl, ix.gsize,
+                        grp1 ? ix.grp : nullptr};
         ix.offsets = lists.offsets;
         ix.cells = lists.cells;
         ix.list_entries = lists.entries;
         ix.tstart = std::move(lists.tstart);
         ix.mem = mem1;
         ix.cmg = cmg1;
+        ix.cfl = cfl1;
         ix.gsize = gsize1;
         if (grp1) {
             ix.grp = grp1;
@@ -549,6 +579,7 @@ void insert_points(Index &ix, const uint32_t *codes, uint64_t n, hipStream_t s) 
         lists = Lists();
         mem1 = nullptr;
         cmg1 = nullptr;
+        cfl1 = nullptr;
         gsize1 = nullptr;
         grp1 = nullptr;
         FL_HIP(hipDeviceSynchronize());
@@ -557,6 +588,7 @@ void insert_points(Index &ix, const uint32_t *codes, uint64_t n, hipStream_t s) 
         dfree(grp1);
         dfree(mem1);
         dfree(cmg1);
+        dfree(cfl1);
         dfree(gsize1);
         dfree(lists.offsets);
         dfree(lists.cells);

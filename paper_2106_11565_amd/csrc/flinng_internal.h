@@ -63,11 +63,16 @@ __host__ __device__ inline uint64_t sm64(uint64_t s, uint64_t i) {
 //   cmg       [R][B][mstride][Rp] uint16 cell-major copy of the groups: the
 //             row of the member in each slot of mem, so a decode pass reads
 //             every candidate's R groups sequentially beside its id
+//   cfl       [R][B][mstride] uint32 the member's groups in repetitions
+//             r+1 and r+2 (mod R), low and high 16 bits: a decode pass of
+//             repetition r reads these 4 bytes per member and gathers the
+//             id and the full row only for the few members whose counts in
+//             those repetitions reach the level
 //   gsize     [R][B]          uint32 members of each cell
 //   hyp       [L*K][dpad]     bf16 hyperplanes (dense families)
 //   hypnorm   [L*K]           fp32 Euclidean norms of the hyperplanes
 // Points inserted after the build (ids N0, N0+1, ...) are added by building
-// new offsets/cells/mem/cmg/gsize arrays beside the old ones and swapping
+// new offsets/cells/mem/cmg/cfl/gsize arrays beside the old ones and swapping
 // them in under `rw` (exclusive), so a query enqueued under `rw` (shared)
 // sees one version; the old arrays are freed once the device is idle.
 struct Index {
@@ -89,6 +94,7 @@ struct Index {
     uint16_t *grp = nullptr;
     uint32_t *mem = nullptr;
     uint16_t *cmg = nullptr;
+    uint32_t *cfl = nullptr;
     uint16_t *hyp = nullptr;
     float *hypnorm = nullptr;
     uint32_t *gsize = nullptr;
@@ -123,7 +129,7 @@ inline uint64_t index_device_bytes(const Index &ix) {
     const uint64_t ncells = (uint64_t)ix.p.R * ix.p.B;
     uint64_t b = (uint64_t)ix.p.L * (nbuckets(ix) + 1) * 4 +
                  cells_alloc_bytes(ix.list_entries, ix.cell_bytes) + ix.grp_cap * ix.Rp * 2 +
-                 ncells * ix.mstride * (4 + 2ull * ix.Rp) + ncells * 4;
+                 ncells * ix.mstride * (8 + 2ull * ix.Rp) + ncells * 4;
     if (is_dense(ix.p.family)) b += (uint64_t)ix.p.L * ix.p.K * (ix.dpad * 2 + 4);
     return b;
 }
@@ -244,6 +250,10 @@ void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals,
 // Build pieces (build.hip).
 void build_groups(Index &ix, hipStream_t s);
 void build_lists(Index &ix, const uint32_t *codes_dev, hipStream_t s);
+// The filter plane cfl of member arrays `mem` (stride mstride) from the
+// point rows `grp`.
+void build_filter(const Index &ix, const uint32_t *mem, const uint16_t *grp, uint32_t mstride,
+                  uint32_t *cfl, hipStream_t s);
 // Add n points (ids ix.N ..) whose codes [n][L] are on the device: groups by
 // the arrival rule, members, reverse index; swaps the new arrays in.  The
 // caller holds ix.insert_mu.  Synchronizes the device.

@@ -58,6 +58,7 @@ struct QArgs {
     const void *cells;
     const uint32_t *mem;   // [R][B][mstride] member ids
     const uint16_t *cmg;   // [R][B][mstride][Rp] member group rows
+    const uint32_t *cfl;   // [R][B][mstride] groups in repetitions r+1, r+2
     uint64_t N;
     const uint32_t *gsize; // [R][B] members of each cell
     uint32_t gmax;         // the largest cell
@@ -108,7 +109,8 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
 
 // misc slots
 enum { M_Q = 0, M_BUFN, M_NGE, M_NALL, M_LEVEL, M_REP, M_KEEPALL, M_NEXT, M_THRLO,
-       M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_NT, M_SCAN0 };
+       M_THRHI, M_LCNT, M_MEMB, M_THI, M_ST_ALL, M_ST_FINAL, M_ST_PASSES, M_NT, M_GATH,
+       M_ST_GATH, M_SCAN0 };
 
 // c / d for c < 2^24 and d >= 1, from the float quotient (within one of the
 // true quotient: c is exact in float and the two roundings of c * (1/d)
@@ -187,7 +189,7 @@ __device__ inline uint64_t shfl64_up1(uint64_t v) {
 // key), the k-th key, and tallies (uniform across the wavefront).
 struct WaveState {
     uint64_t wl, kth;
-    uint32_t n_ge, n_all, members;
+    uint32_t n_ge, n_all, members, gathered;
 };
 
 // Broadcast a 64-bit value from one lane (src uniform across the wavefront).
@@ -407,7 +409,10 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
             const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
             const uint32_t j = j0 + 4 * lane;
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
-            if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
+            if (i < nitems) {
+                ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
+                ws.gathered += (sz - j0 < 256) ? sz - j0 : 256u;
+            }
             const uint64_t slot = (uint64_t)bb * mstride + (j < sz ? j : 0u);
             idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
             load_rows<RP>(cmgr + slot * RP, rows[g]);
@@ -473,6 +478,120 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
                     wave_insert(ws, key, tm, k, lane);
                 }
             }
+        }
+    }
+}
+
+// The group row of one member slot (RP uint16) as (RP + 1) / 2 dwords.
+template <int RP>
+__device__ inline void load_row1(const uint16_t *p, uint32_t (&w)[(RP + 1) / 2]) {
+    if constexpr (RP == 1) {
+        w[0] = *p;
+    } else if constexpr (RP == 2) {
+        w[0] = *reinterpret_cast<const uint32_t *>(p);
+    } else if constexpr (RP == 4) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < RP / 8; ++i) {
+            const uint4 v = reinterpret_cast<const uint4 *>(p)[i];
+            w[4 * i + 0] = v.x;
+            w[4 * i + 1] = v.y;
+            w[4 * i + 2] = v.z;
+            w[4 * i + 3] = v.w;
+        }
+    }
+}
+
+// walk_cells for a pass that keeps only keys with m >= level (R >= 2): a
+// member's m is at most its counts in repetitions r+1 and r+2 (mod R), read
+// from the 4-byte filter word of its slot, so each lane first reads the
+// filter words of its 4 members (one 16-byte load per item) and gathers the
+// id and the full group row only of the members whose counts there reach the
+// level (a few percent of them on the configured workloads).  Every member
+// with m >= level survives the filter, so the keys offered to the top-k, and
+// the tallies, are those of walk_cells.  U items in flight per lane; the
+// survivors' loads of all U items are issued before any is used.
+template <int RP, int U, int T>
+__device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
+                                           const uint32_t *__restrict__ memr,
+                                           const uint16_t *__restrict__ cmgr,
+                                           const uint32_t *__restrict__ cflr, uint32_t R, uint32_t Bp,
+                                           uint32_t mstride, uint32_t level, uint32_t f1b, uint32_t f2b,
+                                           const uint32_t *__restrict__ gsz, uint32_t cpc, uint32_t k,
+                                           int lane, int wave, WaveState &ws) {
+    constexpr int TW = T / 64;
+    constexpr int RW = (RP + 1) / 2;
+    const uint32_t nitems = nl * cpc;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    // counter bytes hold 255 - count: count >= level iff byte < 256 - level
+    const uint32_t lim = 256u - level;
+    uint32_t rb[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
+    for (uint32_t i0 = wv; i0 < nitems; i0 += TW * U) {
+        uint4 fv[U];
+        uint64_t slot[U];
+        uint32_t nv[U];
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            const uint32_t i = i0 + (uint32_t)g * TW;
+            const uint32_t ic = i < nitems ? i : nitems - 1;
+            const uint32_t ci = cpc == 1 ? ic : ic / cpc;
+            const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
+            const uint32_t j0 = (ic - ci * cpc) * 256;
+            const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
+            const uint32_t j = j0 + 4 * lane;
+            nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
+            if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
+            slot[g] = (uint64_t)bb * mstride + (j < sz ? j : 0u);
+            fv[g] = *reinterpret_cast<const uint4 *>(cflr + slot[g]);
+        }
+        // survivors: bit 4g + e for member e of item g
+        uint32_t pass = 0;
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            const uint32_t fw[4] = {fv[g].x, fv[g].y, fv[g].z, fv[g].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t b1 = lds_u8_at(f1b + (fw[e] & 0xFFFFu));
+                const uint32_t b2 = lds_u8_at(f2b + (fw[e] >> 16));
+                if ((uint32_t)e < nv[g] && b1 < lim && b2 < lim) pass |= 1u << (4 * g + e);
+            }
+        }
+        if (!__ballot(pass != 0)) continue;
+        uint32_t xid[4 * U];
+        uint32_t rw[4 * U][RW];
+#pragma unroll
+        for (int m = 0; m < 4 * U; ++m) {
+            xid[m] = 0;
+#pragma unroll
+            for (int i = 0; i < RW; ++i) rw[m][i] = 0;
+            if ((pass >> m) & 1u) {
+                const uint64_t sl = slot[m / 4] + (uint64_t)(m % 4);
+                xid[m] = memr[sl];
+                load_row1<RP>(cmgr + sl * RP, rw[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4 * U; ++m) {
+            const bool pm = (pass >> m) & 1u;
+            const unsigned long long pmask = __ballot(pm);
+            if (!pmask) continue;
+            ws.gathered += (uint32_t)__popcll(pmask);
+            uint32_t t = 0;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                const uint32_t c = rb[r] + ((rw[m][r >> 1] >> (16 * (r & 1))) & 0xFFFFu);
+                const uint32_t tv = (lds_u8_at(c) << 24) | c;
+                t = tv > t ? tv : t;
+            }
+            const unsigned long long gm = __ballot(pm && t < (lim << 24));
+            ws.n_ge += (uint32_t)__popcll(gm);
+            ws.n_all += (uint32_t)__popcll(gm);
+            wave_insert(ws, ((uint64_t)t << 32) | xid[m], gm, k, lane);
         }
     }
 }
@@ -800,6 +919,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
         if (tid == 0) {
             misc[M_ST_ALL] = 0;
             misc[M_ST_FINAL] = 0;
+            misc[M_ST_GATH] = 0;
             misc[M_ST_PASSES] = 0;
         }
         for (;;) {
@@ -819,8 +939,11 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     }
                     // level 1: one pass over repetition R-1 keeping every key
                     // serves both outcomes (m >= 1 for k points, or the
-                    // zero-count completion) when it is not much larger
-                    if (level == 1 &&
+                    // zero-count completion) when it is not much larger.  Not
+                    // where the fast decode filters (R >= 2): its filtered
+                    // pass at level 1 reads a fraction of the bytes and most
+                    // often finds the k keys alone
+                    if (level == 1 && (GK || R < 2) &&
                         (uint64_t)hist[(R - 1) * (L + 1) + 1] * gmax <= 2ull * A.budget) {
                         rep = R - 1;
                         keep = 1;
@@ -836,6 +959,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 misc[M_THRHI] = 0xFFFFFFFFu;
                 misc[M_LCNT] = 0;
                 misc[M_MEMB] = 0;
+                misc[M_GATH] = 0;
             }
             __syncthreads();
             // uniform across the workgroup: kept in scalar registers
@@ -851,10 +975,15 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             // do not fit); each wavefront streams (cell, 256-member chunk)
             // items with several in flight per lane and keeps its own top-k
             // in registers; the lists are merged by rank at the end.
-            WaveState ws{~0ull, ~0ull, 0u, 0u, 0u};
+            WaveState ws{~0ull, ~0ull, 0u, 0u, 0u, 0u};
             // walk items in flight per lane: one where the rows are wide or
             // many wavefronts share a SIMD
             constexpr int WU = (RP >= 4 || (QT == 256 && !PERS)) ? 1 : 2;
+            // the filtered walk: a pass keeping only m >= level, R >= 2
+            constexpr int WF = (RP >= 16 || QT == 256 || PERS) ? 1 : 2;
+            const bool filt = !keep && R >= 2;
+            const uint32_t *cflr = A.cfl + rep * rstride;
+            const uint32_t f1b = ((rep + 1) % R) * Bp, f2b = ((rep + 2) % R) * Bp;
             const uint32_t nrep = hist[rep * (L + 1) + level];
             if (nrep <= CL) {
                 const uint32_t nt = misc[M_NT];
@@ -878,8 +1007,13 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     }
                 }
                 __syncthreads();
-                walk_cells<RP, WU, QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
-                                       A.gsize + rep * B, cpc, k, lane, wave, ws);
+                if (filt)
+                    walk_cells_filtered<RP, WF, QT>(lb, nrep, memr, cmgr, cflr, R, Bp, A.mstride,
+                                                    level, f1b, f2b, A.gsize + rep * B, cpc, k, lane,
+                                                    wave, ws);
+                else
+                    walk_cells<RP, WU, QT>(lb, nrep, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
+                                           A.gsize + rep * B, cpc, k, lane, wave, ws);
             } else {
                 const unsigned long long ltmask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
                 for (uint32_t cb0 = 0; cb0 < B; cb0 += QT) {
@@ -893,8 +1027,13 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     __syncthreads();
                     const uint32_t nl = misc[M_LCNT];
                     if (nl > CL - QT || cb0 + QT >= B) {
-                        walk_cells<RP, WU, QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride, level, keep,
-                                               A.gsize + rep * B, cpc, k, lane, wave, ws);
+                        if (filt)
+                            walk_cells_filtered<RP, WF, QT>(lb, nl, memr, cmgr, cflr, R, Bp,
+                                                            A.mstride, level, f1b, f2b,
+                                                            A.gsize + rep * B, cpc, k, lane, wave, ws);
+                        else
+                            walk_cells<RP, WU, QT>(lb, nl, memr, cmgr, cnt8, R, Bp, A.mstride, level,
+                                                   keep, A.gsize + rep * B, cpc, k, lane, wave, ws);
                         __syncthreads();
                         if (tid == 0) misc[M_LCNT] = 0;
                         __syncthreads();
@@ -909,6 +1048,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 atomicAdd(&misc[M_NGE], ws.n_ge);
                 atomicAdd(&misc[M_NALL], ws.n_all);
                 atomicAdd(&misc[M_MEMB], ws.members);
+                atomicAdd(&misc[M_GATH], ws.gathered);
             }
             __syncthreads();
             if (QW * k <= 64) {
@@ -1016,7 +1156,10 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 atomicAdd(&misc[M_NGE], n_ge);
                 atomicAdd(&misc[M_NALL], n_all);
             }
-            if (tid == 0) atomicAdd(&misc[M_MEMB], (uint32_t)pass_members);
+            if (tid == 0) {
+                atomicAdd(&misc[M_MEMB], (uint32_t)pass_members);
+                atomicAdd(&misc[M_GATH], (uint32_t)pass_members);
+            }
             __syncthreads();
             {
                 const uint32_t nb = misc[M_BUFN];
@@ -1030,7 +1173,10 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             if (tid == 0) {
                 misc[M_ST_ALL] += misc[M_MEMB];
                 misc[M_ST_PASSES] += 1;
-                if (ok || keep) misc[M_ST_FINAL] = misc[M_MEMB];
+                if (ok || keep) {
+                    misc[M_ST_FINAL] = misc[M_MEMB];
+                    misc[M_ST_GATH] = misc[M_GATH];
+                }
             }
             if (ok || keep) {
                 // emit the buffered keys (and, for the fill path, zero cells)
@@ -1098,7 +1244,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             atomicAdd(&A.stats[1], (unsigned long long)misc[M_ST_ALL]);
             atomicAdd(&A.stats[2], (unsigned long long)misc[M_ST_FINAL]);
             atomicAdd(&A.stats[3], (unsigned long long)misc[M_ST_PASSES]);
-            atomicAdd(&A.stats[4], (unsigned long long)misc[M_ST_FINAL]);
+            atomicAdd(&A.stats[4], (unsigned long long)misc[M_ST_GATH]);
         }
         if constexpr (!PERS) break;
         __syncthreads();  // before the next query reuses the LDS state
@@ -1279,6 +1425,7 @@ static QArgs make_args(const Index &ix, const uint32_t *codes, uint64_t nq, uint
     a.cells = ix.cells;
     a.mem = ix.mem;
     a.cmg = ix.cmg;
+    a.cfl = ix.cfl;
     a.N = ix.N;
     a.gsize = ix.gsize;
     a.gmax = ix.gmax;

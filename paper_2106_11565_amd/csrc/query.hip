@@ -508,12 +508,14 @@ __device__ inline void load_row1(const uint16_t *p, uint32_t (&w)[(RP + 1) / 2])
 // walk_cells for a pass that keeps only keys with m >= level (R >= 2): a
 // member's m is at most its counts in repetitions r+1 and r+2 (mod R), read
 // from the 4-byte filter word of its slot, so each lane first reads the
-// filter words of its 4 members (one 16-byte load per item) and gathers the
-// id and the full group row only of the members whose counts there reach the
-// level (a few percent of them on the configured workloads).  Every member
-// with m >= level survives the filter, so the keys offered to the top-k, and
-// the tallies, are those of walk_cells.  U items in flight per lane; the
-// survivors' loads of all U items are issued before any is used.
+// filter words of its 4 members of each of U items (one 16-byte load per
+// item, all in flight together) and gathers the id and the full group row
+// only of the members whose counts there reach the level (about 1% of them
+// on the ReLU and URL workloads).  The survivors are then taken one per lane
+// per round (a lane with several takes them in later rounds), so a batch of
+// U items costs two rounds of memory latency in the common case.  Every
+// member with m >= level survives the filter, so the keys offered to the
+// top-k, and the tallies, are those of walk_cells.
 template <int RP, int U, int T>
 __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
                                            const uint32_t *__restrict__ memr,
@@ -550,7 +552,7 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
             fv[g] = *reinterpret_cast<const uint4 *>(cflr + slot[g]);
         }
         // survivors: bit 4g + e for member e of item g
-        uint32_t pass = 0;
+        uint32_t pend = 0;
 #pragma unroll
         for (int g = 0; g < U; ++g) {
             const uint32_t fw[4] = {fv[g].x, fv[g].y, fv[g].z, fv[g].w};
@@ -558,40 +560,36 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
             for (int e = 0; e < 4; ++e) {
                 const uint32_t b1 = lds_u8_at(f1b + (fw[e] & 0xFFFFu));
                 const uint32_t b2 = lds_u8_at(f2b + (fw[e] >> 16));
-                if ((uint32_t)e < nv[g] && b1 < lim && b2 < lim) pass |= 1u << (4 * g + e);
+                if ((uint32_t)e < nv[g] && b1 < lim && b2 < lim) pend |= 1u << (4 * g + e);
             }
         }
-        if (!__ballot(pass != 0)) continue;
-        uint32_t xid[4 * U];
-        uint32_t rw[4 * U][RW];
+        while (__ballot(pend != 0)) {
+            const bool act = pend != 0;
+            const uint32_t m = act ? (uint32_t)__builtin_ctz(pend) : 0u;
+            pend &= pend - 1;
+            uint64_t sl = slot[0];
 #pragma unroll
-        for (int m = 0; m < 4 * U; ++m) {
-            xid[m] = 0;
+            for (int g = 1; g < U; ++g) sl = (m >> 2) == (uint32_t)g ? slot[g] : sl;
+            sl += m & 3u;
+            uint32_t xid = 0, rw[RW];
 #pragma unroll
-            for (int i = 0; i < RW; ++i) rw[m][i] = 0;
-            if ((pass >> m) & 1u) {
-                const uint64_t sl = slot[m / 4] + (uint64_t)(m % 4);
-                xid[m] = memr[sl];
-                load_row1<RP>(cmgr + sl * RP, rw[m]);
+            for (int i = 0; i < RW; ++i) rw[i] = 0;
+            if (act) {
+                xid = memr[sl];
+                load_row1<RP>(cmgr + sl * RP, rw);
             }
-        }
-#pragma unroll
-        for (int m = 0; m < 4 * U; ++m) {
-            const bool pm = (pass >> m) & 1u;
-            const unsigned long long pmask = __ballot(pm);
-            if (!pmask) continue;
-            ws.gathered += (uint32_t)__popcll(pmask);
+            ws.gathered += (uint32_t)__popcll(__ballot(act));
             uint32_t t = 0;
 #pragma unroll
             for (int r = 0; r < RP; ++r) {
-                const uint32_t c = rb[r] + ((rw[m][r >> 1] >> (16 * (r & 1))) & 0xFFFFu);
+                const uint32_t c = rb[r] + ((rw[r >> 1] >> (16 * (r & 1))) & 0xFFFFu);
                 const uint32_t tv = (lds_u8_at(c) << 24) | c;
                 t = tv > t ? tv : t;
             }
-            const unsigned long long gm = __ballot(pm && t < (lim << 24));
+            const unsigned long long gm = __ballot(act && t < (lim << 24));
             ws.n_ge += (uint32_t)__popcll(gm);
             ws.n_all += (uint32_t)__popcll(gm);
-            wave_insert(ws, ((uint64_t)t << 32) | xid[m], gm, k, lane);
+            wave_insert(ws, ((uint64_t)t << 32) | xid, gm, k, lane);
         }
     }
 }
@@ -980,7 +978,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             // many wavefronts share a SIMD
             constexpr int WU = (RP >= 4 || (QT == 256 && !PERS)) ? 1 : 2;
             // the filtered walk: a pass keeping only m >= level, R >= 2
-            constexpr int WF = (RP >= 16 || QT == 256 || PERS) ? 1 : 2;
+            constexpr int WF = (QT == 256 || PERS) ? (WAVES >= 8 ? 1 : 2) : 4;
             const bool filt = !keep && R >= 2;
             const uint32_t *cflr = A.cfl + rep * rstride;
             const uint32_t f1b = ((rep + 1) % R) * Bp, f2b = ((rep + 2) % R) * Bp;
@@ -1041,7 +1039,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
             }
             // merge the per-wave lists: when they fit in one wavefront, one
-            // sort across it; else the rank of each key among all lists
+            // sort across it; else the rank of each key among all keys
             uint64_t *wlist = buf + k;  // one k-key list per wavefront
             if ((uint32_t)lane < k) wlist[wave * k + lane] = ws.wl;
             if (lane == 0) {
@@ -1062,19 +1060,15 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 }
                 if (fin && wave != 0) break;
             } else if ((uint32_t)tid < QW * k) {
-                const uint32_t w = tid / k, i = tid % k;
-                const uint64_t key = wlist[w * k + i];
+                // rank = the keys of all lists below this one (keys are
+                // distinct; empty entries, ~0, are below none): independent
+                // broadcast reads of the whole set rather than dependent
+                // binary searches
+                const uint64_t key = wlist[tid];
                 if (key != ~0ull) {
-                    uint32_t rank = i;
-                    for (uint32_t w2 = 0; w2 < (uint32_t)QW; ++w2) {
-                        if (w2 == w) continue;
-                        uint32_t lo = 0, hi = k;  // keys of list w2 below `key`
-                        while (lo < hi) {
-                            const uint32_t mid = (lo + hi) >> 1;
-                            if (wlist[w2 * k + mid] < key) lo = mid + 1; else hi = mid;
-                        }
-                        rank += lo;
-                    }
+                    uint32_t rank = 0;
+#pragma unroll 8
+                    for (uint32_t j = 0; j < QW * k; ++j) rank += (wlist[j] < key) ? 1u : 0u;
                     if (rank < k) buf[rank] = key;
                 }
             }

@@ -406,16 +406,18 @@ __device__ inline void walk_cells(const uint32_t *lbs, uint32_t nl, const uint32
             const uint32_t ci = cpc == 1 ? ic : ic / cpc;
             const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
             const uint32_t j0 = (ic - ci * cpc) * 256;
-            const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
             const uint32_t j = j0 + 4 * lane;
+            // slots clamped into the cell's stride, so that the loads need
+            // not wait for the size; slots past it are masked by nv
+            const uint64_t slot = (uint64_t)bb * mstride + (j < mstride ? j : 0u);
+            idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
+            load_rows<RP>(cmgr + slot * RP, rows[g]);
+            const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
-            if (i < nitems) {
+            if (i < nitems && j0 < sz) {
                 ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
                 ws.gathered += (sz - j0 < 256) ? sz - j0 : 256u;
             }
-            const uint64_t slot = (uint64_t)bb * mstride + (j < sz ? j : 0u);
-            idv[g] = *reinterpret_cast<const uint4 *>(memr + slot);
-            load_rows<RP>(cmgr + slot * RP, rows[g]);
         }
         // repetition r's counters start at rb[r]; the padding repetitions
         // r >= R repeat repetition R-1 (its group is repeated in the rows)
@@ -535,21 +537,30 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
     for (int r = 0; r < RP; ++r) rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
     for (uint32_t i0 = wv; i0 < nitems; i0 += TW * U) {
         uint4 fv[U];
-        uint64_t slot[U];
-        uint32_t nv[U];
+        uint32_t slot[U];  // within the repetition: B * mstride < 2^32
+        uint32_t nv[U], szv[U];
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            // the filter words (clamped into the cell's stride) and the
+            // cell's size are loaded together; slots past the size are
+            // padding, masked out below
+            const uint32_t i = i0 + (uint32_t)g * TW;
+            const uint32_t ic = i < nitems ? i : nitems - 1;
+            const uint32_t ci = cpc == 1 ? ic : ic / cpc;
+            const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
+            const uint32_t j = (ic - ci * cpc) * 256 + 4 * lane;
+            slot[g] = bb * mstride + (j < mstride ? j : 0u);
+            fv[g] = *reinterpret_cast<const uint4 *>(cflr + slot[g]);
+            szv[g] = __builtin_amdgcn_readfirstlane(gsz[bb]);
+        }
 #pragma unroll
         for (int g = 0; g < U; ++g) {
             const uint32_t i = i0 + (uint32_t)g * TW;
             const uint32_t ic = i < nitems ? i : nitems - 1;
             const uint32_t ci = cpc == 1 ? ic : ic / cpc;
-            const uint32_t bb = __builtin_amdgcn_readfirstlane(lbs[ci]);
-            const uint32_t j0 = (ic - ci * cpc) * 256;
-            const uint32_t sz = __builtin_amdgcn_readfirstlane(gsz[bb]);
-            const uint32_t j = j0 + 4 * lane;
+            const uint32_t j0 = (ic - ci * cpc) * 256, j = j0 + 4 * lane, sz = szv[g];
             nv[g] = (i < nitems && j < sz) ? ((sz - j < 4) ? sz - j : 4u) : 0u;
-            if (i < nitems) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
-            slot[g] = (uint64_t)bb * mstride + (j < sz ? j : 0u);
-            fv[g] = *reinterpret_cast<const uint4 *>(cflr + slot[g]);
+            if (i < nitems && j0 < sz) ws.members += (sz - j0 < 256) ? sz - j0 : 256u;
         }
         // survivors: bit 4g + e for member e of item g
         uint32_t pend = 0;
@@ -567,7 +578,7 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
             const bool act = pend != 0;
             const uint32_t m = act ? (uint32_t)__builtin_ctz(pend) : 0u;
             pend &= pend - 1;
-            uint64_t sl = slot[0];
+            uint32_t sl = slot[0];
 #pragma unroll
             for (int g = 1; g < U; ++g) sl = (m >> 2) == (uint32_t)g ? slot[g] : sl;
             sl += m & 3u;
@@ -576,7 +587,7 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
             for (int i = 0; i < RW; ++i) rw[i] = 0;
             if (act) {
                 xid = memr[sl];
-                load_row1<RP>(cmgr + sl * RP, rw);
+                load_row1<RP>(cmgr + (uint64_t)sl * RP, rw);
             }
             ws.gathered += (uint32_t)__popcll(__ballot(act));
             uint32_t t = 0;
@@ -979,7 +990,7 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
             constexpr int WU = (RP >= 4 || (QT == 256 && !PERS)) ? 1 : 2;
             // the filtered walk: a pass keeping only m >= level, R >= 2
             constexpr int WF = (QT == 256 || PERS) ? (WAVES >= 8 ? 1 : 2) : 4;
-            const bool filt = !keep && R >= 2;
+            const bool filt = !keep && R >= 2 && rstride < (1ull << 32);  // 32-bit slots
             const uint32_t *cflr = A.cfl + rep * rstride;
             const uint32_t f1b = ((rep + 1) % R) * Bp, f2b = ((rep + 2) % R) * Bp;
             const uint32_t nrep = hist[rep * (L + 1) + level];

@@ -71,6 +71,10 @@ def parse():
                     help="measure |v32 - v| / (|x| |w|) of the bf16 projections on the ReLU "
                          "workload (all queries and a sample of indexed rows)")
     ap.add_argument("--rates", default="", help="comma-separated Poisson arrival rates (queries/s)")
+    ap.add_argument("--max-batch", type=int, default=SERVER["max_batch"],
+                    help="server: queries per launched batch")
+    ap.add_argument("--max-inflight", type=int, default=SERVER["max_inflight"],
+                    help="server: batches on the GPU at once")
     return ap.parse_args()
 
 
@@ -394,9 +398,13 @@ class DeviceRequests:
         self.fl.check(self.fl.lib().flinng_serve_wait(srv_h, ticket, None, None, -1))
 
 
+SERVER = {"max_inflight": 2, "max_batch": 4096}
+
+
 def make_server(fl, ws, persistent=False):
-    return fl.Server([w.index for w in ws], mem_budget=8 << 30, max_inflight=4,
-                     max_batch=4096, persistent=persistent)
+    return fl.Server([w.index for w in ws], mem_budget=8 << 30,
+                     max_inflight=SERVER["max_inflight"], max_batch=SERVER["max_batch"],
+                     persistent=persistent)
 
 
 def served_device_steps(fl, torch, ws, reqs, steps, warmup, refs):
@@ -658,6 +666,7 @@ def cpu_baseline_single(w, ids, sc, seconds):
 
 def main():
     args = parse()
+    SERVER["max_batch"], SERVER["max_inflight"] = args.max_batch, args.max_inflight
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the query path is "
               "replicated per GPU with no exchange, so no multi-GPU figure is produced.",
@@ -723,7 +732,8 @@ def main_mixed(args, torch, fl, configs):
                                 "B": w.B, "bucket_bits": None if w.dense else w.b,
                                 "K_L": "tuned (fastest of the sweep with R1@10 >= 0.9)"
                                 if w.tuned else "as configured"} for w in ws],
-                   "server": {"max_inflight": 4, "max_batch": 4096, "mem_budget_GiB": 8}},
+                   "server": {"max_inflight": SERVER["max_inflight"],
+                              "max_batch": SERVER["max_batch"], "mem_budget_GiB": 8}},
         "served": served,
         "plain": {"per_family": plain_res, "mixed_ms_per_step": round(plain_ms, 4),
                   "mixed_qps": round(nq_all / (plain_ms / 1e3), 1)},

@@ -232,11 +232,13 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
  *           be NULL).
  * Returns once the work is enqueued on `stream`.  FLINNG_EINVAL when the
  * batch needs more scratch than the array holds (about nq*L*4 bytes plus,
- * for dense indexes, nq*(4 + 8*ceil(K*L/32)) bytes and, unless bf16 rows
- * with dim a multiple of 32 are used in place, the bf16 operand planes of
- * nq*dim*2 bytes, three for fp32 rows): split the batch.  Calls that
- * overlap on one GPU share the array and race: serialize them (one stream,
- * or events).
+ * for dense indexes, nq*(4 + 8*ceil(K*L/32)) bytes, for bf16 batches small
+ * enough that the projection splits its k range into ns pieces
+ * (ns <= ceil(dim/128)) ns*nq*K*L*4 bytes of partial projections, and,
+ * unless bf16 rows with dim a multiple of 32 are used in place, the bf16
+ * operand planes of nq*dim*2 bytes, three for fp32 rows): split the batch.
+ * Calls that overlap on one GPU share the array and race: serialize them
+ * (one stream, or events).
  */
 int flinng_query_noalloc(const flinng_index *idx, const flinng_input *q, uint32_t k,
                          uint32_t *ids, uint32_t *scores, uint32_t persistent, void *stream);

@@ -81,7 +81,7 @@ struct QArgs {
 struct QLayout {
     uint32_t cnt_words, hist_words, cap;
     size_t off_cnt, off_hist, off_pre, off_pree, off_start, off_end, off_buf, off_lb, off_lp, off_tl,
-        off_misc, total;
+        off_fp, off_fs, off_misc, total;
 };
 
 // gk: the general-k decode, which also needs the per-thread prefix slots.
@@ -101,6 +101,11 @@ __host__ __device__ inline QLayout q_layout(uint32_t L, uint32_t R, uint32_t Bp,
     l.off_lb = o;    o += cl_for(T) * 4;
     l.off_lp = o;    o += gk ? (size_t)T * 4 : 0;
     l.off_tl = o;    o += gk ? 0 : (size_t)tl_for(T) * 4;
+    // the flattened walk of the 1024-thread fast path: 4-rounded prefix
+    // sums and sizes of the listed cells
+    const bool flat = !gk && T == 1024;
+    l.off_fp = o;    o += flat ? (size_t)(cl_for(T) + 1) * 4 : 0;
+    l.off_fs = o;    o += flat ? (size_t)cl_for(T) * 4 : 0;
     l.off_misc = o;  o += 64 * 4;
     l.off_hist = o;  o += (size_t)l.hist_words * 4;  // last: only its size varies with hc
     l.total = (o + 15) & ~(size_t)15;
@@ -605,6 +610,93 @@ __device__ inline void walk_cells_filtered(const uint32_t *lbs, uint32_t nl,
     }
 }
 
+// walk_cells_filtered over the listed cells' members as one flattened
+// sequence (each cell's run padded to a multiple of 4 inside its stride):
+// items of 256 consecutive positions, so that a wavefront's lanes stay busy
+// however the cell sizes fall (cells of 122 members would leave half the
+// lanes of a per-cell item idle, cells of 305 a second item nearly empty).
+// A lane finds the cell of its 4 positions by a binary search over the
+// prefix sums fp (LDS), then reads their filter words; survivors as in
+// walk_cells_filtered.
+template <int RP, int U, int T>
+__device__ inline void walk_flat_filtered(const uint32_t *lbs, const uint32_t *fp, const uint32_t *fs,
+                                          uint32_t nl, uint32_t total,
+                                          const uint32_t *__restrict__ memr,
+                                          const uint16_t *__restrict__ cmgr,
+                                          const uint32_t *__restrict__ cflr, uint32_t R, uint32_t Bp,
+                                          uint32_t mstride, uint32_t level, uint32_t f1b, uint32_t f2b,
+                                          uint32_t k, int lane, int wave, WaveState &ws) {
+    constexpr int TW = T / 64;
+    constexpr int RW = (RP + 1) / 2;
+    const uint32_t nitems = (total + 255) / 256;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    const uint32_t lim = 256u - level;
+    uint32_t rb[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) rb[r] = ((uint32_t)r < R ? (uint32_t)r : R - 1) * Bp;
+    for (uint32_t i0 = wv; i0 < nitems; i0 += TW * U) {
+        uint4 fv[U];
+        uint32_t slot[U];  // within the repetition: B * mstride < 2^32
+        uint32_t nv[U];
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            const uint32_t i = i0 + (uint32_t)g * TW;
+            const uint32_t pos = i * 256 + 4 * lane;
+            const bool valid = i < nitems && pos < total;
+            const uint32_t pp = valid ? pos : 0u;
+            uint32_t lo = 0, hi = nl;  // the last cell whose run starts at or before pp
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (fp[mid] <= pp) lo = mid; else hi = mid;
+            }
+            const uint32_t o = pp - fp[lo], sz = fs[lo];
+            nv[g] = (valid && o < sz) ? ((sz - o < 4) ? sz - o : 4u) : 0u;
+            slot[g] = lbs[lo] * mstride + o;
+            fv[g] = *reinterpret_cast<const uint4 *>(cflr + slot[g]);
+        }
+        uint32_t pend = 0;
+#pragma unroll
+        for (int g = 0; g < U; ++g) {
+            const uint32_t fw[4] = {fv[g].x, fv[g].y, fv[g].z, fv[g].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ws.members += (uint32_t)__popcll(__ballot((uint32_t)e < nv[g]));
+                const uint32_t b1 = lds_u8_at(f1b + (fw[e] & 0xFFFFu));
+                const uint32_t b2 = lds_u8_at(f2b + (fw[e] >> 16));
+                if ((uint32_t)e < nv[g] && b1 < lim && b2 < lim) pend |= 1u << (4 * g + e);
+            }
+        }
+        while (__ballot(pend != 0)) {
+            const bool act = pend != 0;
+            const uint32_t m = act ? (uint32_t)__builtin_ctz(pend) : 0u;
+            pend &= pend - 1;
+            uint32_t sl = slot[0];
+#pragma unroll
+            for (int g = 1; g < U; ++g) sl = (m >> 2) == (uint32_t)g ? slot[g] : sl;
+            sl += m & 3u;
+            uint32_t xid = 0, rw[RW];
+#pragma unroll
+            for (int i = 0; i < RW; ++i) rw[i] = 0;
+            if (act) {
+                xid = memr[sl];
+                load_row1<RP>(cmgr + (uint64_t)sl * RP, rw);
+            }
+            ws.gathered += (uint32_t)__popcll(__ballot(act));
+            uint32_t t = 0;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                const uint32_t c = rb[r] + ((rw[r >> 1] >> (16 * (r & 1))) & 0xFFFFu);
+                const uint32_t tv = (lds_u8_at(c) << 24) | c;
+                t = tv > t ? tv : t;
+            }
+            const unsigned long long gm = __ballot(act && t < (lim << 24));
+            ws.n_ge += (uint32_t)__popcll(gm);
+            ws.n_all += (uint32_t)__popcll(gm);
+            wave_insert(ws, ((uint64_t)t << 32) | xid, gm, k, lane);
+        }
+    }
+}
+
 // m and c* of one member from its group row (general-k path).
 __device__ inline void slot_min_cell(const uint16_t *row, uint32_t R, uint32_t Bp, const uint8_t *cnt8,
                                      uint32_t &m, uint32_t &cs) {
@@ -1016,7 +1108,22 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                     }
                 }
                 __syncthreads();
-                if (filt)
+                if (QT == 1024 && filt) {
+                    // sizes and 4-rounded prefix sums of the listed cells
+                    // (nrep <= CL = QT: one cell per thread)
+                    uint32_t *fp = reinterpret_cast<uint32_t *>(lds + lay.off_fp);
+                    uint32_t *fs = reinterpret_cast<uint32_t *>(lds + lay.off_fs);
+                    const uint32_t csz = (uint32_t)tid < nrep ? A.gsize[rep * B + lb[tid]] : 0u;
+                    uint32_t ftot;
+                    const uint32_t fex = wg_excl_scan<QT>((csz + 3) & ~3u, scr, &ftot);
+                    if ((uint32_t)tid < nrep) {
+                        fp[tid] = fex;
+                        fs[tid] = csz;
+                    }
+                    __syncthreads();
+                    walk_flat_filtered<RP, WF, QT>(lb, fp, fs, nrep, ftot, memr, cmgr, cflr, R, Bp,
+                                                   A.mstride, level, f1b, f2b, k, lane, wave, ws);
+                } else if (filt)
                     walk_cells_filtered<RP, WF, QT>(lb, nrep, memr, cmgr, cflr, R, Bp, A.mstride,
                                                     level, f1b, f2b, A.gsize + rep * B, cpc, k, lane,
                                                     wave, ws);

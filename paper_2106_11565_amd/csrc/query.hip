@@ -1184,9 +1184,21 @@ __global__ __launch_bounds__(QT, WAVES) void query_kernel(QArgs A) {
                 // binary searches
                 const uint64_t key = wlist[tid];
                 if (key != ~0ull) {
-                    uint32_t rank = 0;
-#pragma unroll 8
-                    for (uint32_t j = 0; j < QW * k; ++j) rank += (wlist[j] < key) ? 1u : 0u;
+                    // (1024 threads: sixteen reads issued before any
+                    // compare, so the LDS latency is paid once per sixteen
+                    // keys; the 256-thread kernels lack the registers)
+                    constexpr uint32_t RB16 = QT == 1024 ? 16u : 1u;
+                    const uint32_t nkeys = QW * k;
+                    uint32_t rank = 0, j = 0;
+                    if constexpr (RB16 > 1)
+                    for (; j + 16 <= nkeys; j += 16) {
+                        uint64_t v[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) v[u] = wlist[j + u];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) rank += (v[u] < key) ? 1u : 0u;
+                    }
+                    for (; j < nkeys; ++j) rank += (wlist[j] < key) ? 1u : 0u;
                     if (rank < k) buf[rank] = key;
                 }
             }

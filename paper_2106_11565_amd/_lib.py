@@ -81,6 +81,13 @@ def lib():
             raise ImportError(
                 f"{LIB_PATH} is not built; run `python -m paper_2106_11565_amd.build` "
                 "(the HIP library is required: there is no CPU fallback)")
+        # one HIP runtime per process: the device pointers and streams handed
+        # to the library come from torch, so torch's runtime is loaded first
+        # and the library binds to it (same soname)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         sig = {

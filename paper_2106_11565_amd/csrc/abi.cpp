@@ -115,6 +115,7 @@ static void free_index(Index *ix) {
     if (ix->cfl) (void)hipFree(ix->cfl);
     if (ix->hyp) (void)hipFree(ix->hyp);
     if (ix->hypnorm) (void)hipFree(ix->hypnorm);
+    if (ix->hypt) (void)hipFree(ix->hypt);
     if (ix->gsize) (void)hipFree(ix->gsize);
     delete ix;
 }
@@ -176,6 +177,8 @@ static void build_impl(const flinng_params *p, const flinng_input *data, hipStre
         if (dense) {
             ix->hyp = dmalloc<uint16_t>((uint64_t)p->L * p->K * ix->dpad, bytes);
             ix->hypnorm = dmalloc<float>((uint64_t)p->L * p->K, bytes);
+            if (p->family == FLINNG_SRP_BF16)
+                ix->hypt = dmalloc<uint16_t>(((uint64_t)p->L * p->K + 15) / 16 * 16 * ix->dpad, bytes);
             srp_make_hyperplanes(*ix, s);
         }
         // hash all points (in chunks to bound scratch memory)

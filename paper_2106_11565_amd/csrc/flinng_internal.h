@@ -71,6 +71,9 @@ __host__ __device__ inline uint64_t sm64(uint64_t s, uint64_t i) {
 //   gsize     [R][B]          uint32 members of each cell
 //   hyp       [L*K][dpad]     bf16 hyperplanes (dense families)
 //   hypnorm   [L*K]           fp32 Euclidean norms of the hyperplanes
+//   hypt      [ceil(L*K/16)][dpad/32][16][32]  bf16 family: the hyperplanes
+//             again, in 16 x 32 tiles (one MFMA operand fragment each, 1 KB
+//             contiguous; rows past L*K zero)
 // Points inserted after the build (ids N0, N0+1, ...) are added by building
 // new offsets/cells/mem/cmg/cfl/gsize arrays beside the old ones and swapping
 // them in under `rw` (exclusive), so a query enqueued under `rw` (shared)
@@ -97,6 +100,7 @@ struct Index {
     uint32_t *cfl = nullptr;
     uint16_t *hyp = nullptr;
     float *hypnorm = nullptr;
+    uint16_t *hypt = nullptr;
     uint32_t *gsize = nullptr;
     uint32_t gmax = 0;                    // the largest cell
     std::vector<uint32_t> gsize_host;     // host copy of gsize
@@ -131,6 +135,7 @@ inline uint64_t index_device_bytes(const Index &ix) {
                  cells_alloc_bytes(ix.list_entries, ix.cell_bytes) + ix.grp_cap * ix.Rp * 2 +
                  ncells * ix.mstride * (8 + 2ull * ix.Rp) + ncells * 4;
     if (is_dense(ix.p.family)) b += (uint64_t)ix.p.L * ix.p.K * (ix.dpad * 2 + 4);
+    if (ix.p.family == FLINNG_SRP_BF16) b += ((uint64_t)ix.p.L * ix.p.K + 15) / 16 * 16 * ix.dpad * 2;
     return b;
 }
 

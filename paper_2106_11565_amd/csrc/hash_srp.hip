@@ -6,6 +6,9 @@
 // the table's bucket is sum_j bit_j 2^j.  Hashing is shared by every filter
 // and done once per point or query (Section 6, Implementation).
 //
+// bf16 rows take one fused kernel (srp_fused_kernel) for all of the steps
+// below; fp32 rows take them as three kernels.
+//
 // Pipeline (one batch of n rows, H = L*K hyperplanes):
 //   1. prep: bf16 operand planes (fp32 rows split exactly into 3 bf16 terms)
 //      and fp32 row norms.
@@ -78,6 +81,18 @@ __global__ void hypnorm_kernel(const uint16_t *__restrict__ w, float *__restrict
     if (lane == 0) nw[h] = sqrtf(s);
 }
 
+// The tiled copy: element (h, i) at ((h / 16) * (dpad / 32) + i / 32) * 512
+// + (h % 16) * 32 + i % 32, zero for h >= H.
+__global__ void hyp_tile_kernel(const uint16_t *__restrict__ w, uint16_t *__restrict__ wt,
+                                uint32_t H, uint32_t dpad) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t hp = (H + 15) / 16 * 16;
+    if (id >= hp * dpad) return;
+    const uint32_t h = (uint32_t)(id / dpad), i = (uint32_t)(id % dpad);
+    const uint64_t o = ((uint64_t)(h / 16) * (dpad / 32) + i / 32) * 512 + (h % 16) * 32 + i % 32;
+    wt[o] = h < H ? w[(uint64_t)h * dpad + i] : (uint16_t)0;
+}
+
 void srp_make_hyperplanes(Index &ix, hipStream_t s) {
     const uint32_t H = ix.p.L * ix.p.K;
     uint64_t total = (uint64_t)H * ix.dpad;
@@ -87,11 +102,18 @@ void srp_make_hyperplanes(Index &ix, hipStream_t s) {
     hipLaunchKernelGGL(hypnorm_kernel, dim3((H + 3) / 4), dim3(256), 0, s, ix.hyp,
                        ix.hypnorm, H, ix.dpad);
     FL_CHECK_LAUNCH();
+    if (ix.hypt) {
+        const uint64_t tot = (uint64_t)(H + 15) / 16 * 16 * ix.dpad;
+        hipLaunchKernelGGL(hyp_tile_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                           ix.hyp, ix.hypt, H, ix.dpad);
+        FL_CHECK_LAUNCH();
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Prep: one wavefront per row.  Writes nsplit bf16 planes [n][dpad] (unless
-// planes == nullptr) and the row norm, rounded to fp32.  fp32 values are
+// planes == nullptr) and the row norm, rounded to fp32 (unless nx ==
+// nullptr), and clears the sign and flag words and the counters (those given).  fp32 values are
 // split by truncation: x = x1 + x2 + x3, each a bf16 (exact except below
 // 2^-133, which the denormal allowance of tau covers).
 // The sum of squares is accumulated in FP64: the square of any fp32 or bf16
@@ -113,7 +135,7 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
         bits[row * Hw + w] = 0u;
         flags[row * Hw + w] = 0u;
     }
-    if (row == 0 && lane < 2) ctr[lane] = 0ull;
+    if (ctr && row == 0 && lane < 2) ctr[lane] = 0ull;
     const uint64_t plane_stride = n * dpad;
     double s = 0.0;
     if (!F32 && planes == nullptr && d == dpad) {
@@ -131,7 +153,7 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
             }
         }
         s = wave_sum_f64(s);
-        if (lane == 0) nx[row] = (float)sqrt(s);
+        if (lane == 0 && nx) nx[row] = (float)sqrt(s);
         return;
     }
     for (uint32_t i = lane; i < dpad; i += 64) {
@@ -162,7 +184,7 @@ __global__ void prep_kernel(const void *__restrict__ xin, uint64_t n, uint32_t d
         }
     }
     s = wave_sum_f64(s);
-    if (lane == 0) nx[row] = (float)sqrt(s);
+    if (lane == 0 && nx) nx[row] = (float)sqrt(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,309 +288,6 @@ __global__ __launch_bounds__(64 * WM * WN) void srp_mfma_kernel(
     if ((lane % 16) == 0 && flagged) atomicAdd(nflag, flagged);
 }
 
-// The same products for one bf16 operand plane with both operands staged in
-// LDS: a 256-thread workgroup computes a 128 x 128 tile (four wavefronts of
-// 64 x 64) over one range of k.  Each 64-wide k step of the 128 rows and the
-// 128 hyperplanes is loaded once per workgroup (four 16-byte loads per thread
-// and operand), prefetched into registers while the previous step is
-// multiplied, and double-buffered in LDS with rows padded against bank
-// conflicts.  Accumulation is chunked: every 128 consecutive k accumulate into
-// a fresh partial (MFMA accumulate), and the partials are added in fp32 by the
-// wavefront.  A product then passes through at most 128 roundings inside its
-// chunk (whatever order an instruction sums its 32 products and its
-// accumulator in) plus one per chunk, so |v32 - v| <= gamma_m * sum|x_i w_i|
-// with m = min(128, d) + ceil(d / 128) (srp_lds_terms), far below the gamma_d
-// of one long accumulation chain.
-//
-// Split k: small batches give fewer tiles than the chip has compute units,
-// and a long k loop is a chain of dependent steps, so the k range is cut into
-// ns pieces of whole chunks, each its own workgroup, writing fp32 partial
-// projections that srp_finish_kernel adds in piece order.  A product then
-// passes through ceil(kpiece / 128) chunk additions and ns - 1 piece
-// additions, which for kpiece a multiple of 128 is at most ceil(d / 128): the
-// bound above holds unchanged.
-//
-// Workgroup order: the hardware hands consecutive workgroup ids to the eight
-// XCDs in turn; ids are renumbered so that the column tiles of one row tile
-// (which read the same rows) run on one XCD, close in time, and share its L2.
-constexpr int LT = 128;          // tile rows and hyperplanes
-constexpr int LK = 64;           // k per pipeline step (two 32-wide MFMA slices)
-constexpr int LROW = LK + 8;     // bf16 per LDS row (16 bytes of padding)
-constexpr int LCHK = 128;        // k per accumulation chunk
-constexpr int LPC = LT * LK / 8 / 256;  // 16-byte pieces per thread and operand
-
-// Roundings a product passes through in srp_mfma_lds_kernel (see above).
-inline uint32_t srp_lds_terms(uint32_t dpad) {
-    return (dpad < (uint32_t)LCHK ? dpad : (uint32_t)LCHK) + (dpad + LCHK - 1) / LCHK;
-}
-
-// How the LDS kernel covers n rows: tiles of 128 x 128 and k pieces.
-struct SrpSplit {
-    uint32_t nct, nrt, ns, kpiece;
-};
-
-static SrpSplit srp_split(uint32_t H, uint64_t n, uint32_t dpad) {
-    SrpSplit sp;
-    sp.nct = (H + LT - 1) / LT;
-    sp.nrt = (uint32_t)((n + LT - 1) / LT);
-    const uint64_t tiles = (uint64_t)sp.nct * sp.nrt;
-    const uint32_t nch = (dpad + LCHK - 1) / LCHK;
-    // Two workgroups fit on each of the 256 compute units.  Estimated time:
-    // (rounds of resident workgroups) x (chunks per piece) x the time of one
-    // chunk at full load (about 2.8 us measured), plus writing and reading
-    // the fp32 partials of more than one piece (at about 5000 bytes per ns).
-    constexpr uint64_t SLOTS = 512;
-    constexpr double CHUNK_NS = 2800.0, NS_PER_BYTE = 1.0 / 5000.0;
-    uint32_t best = 1;
-    double best_cost = 0.0;
-    for (uint32_t ns = 1; ns <= nch; ++ns) {
-        const uint32_t cps = (nch + ns - 1) / ns;
-        if (ns > 1 && (nch + cps - 1) / cps < ns) continue;  // same split as fewer pieces
-        const uint64_t rounds = (tiles * ns + SLOTS - 1) / SLOTS;
-        double cost = (double)rounds * cps * CHUNK_NS;
-        if (ns > 1) cost += NS_PER_BYTE * 8.0 * ns * (double)n * H;
-        if (ns == 1 || cost < best_cost) {
-            best_cost = cost;
-            best = ns;
-        }
-    }
-    const uint32_t cps = (nch + best - 1) / best;
-    sp.kpiece = cps * LCHK;
-    sp.ns = (nch + cps - 1) / cps;
-    return sp;
-}
-
-__global__ __launch_bounds__(256, 2) void srp_mfma_lds_kernel(
-    const uint16_t *__restrict__ planes, uint32_t ld, const uint16_t *__restrict__ w,
-    uint32_t dpad, const float *__restrict__ nx, const float *__restrict__ nw, uint64_t n,
-    uint32_t H, uint32_t Hw, float gamma, float tau_abs, uint32_t nct, uint32_t nrt,
-    uint32_t kpiece, float *__restrict__ part, uint16_t *__restrict__ bits16,
-    uint16_t *__restrict__ flags16, unsigned long long *__restrict__ nflag,
-    float *__restrict__ proj) {
-    __shared__ __align__(16) uint16_t sa[2][LT * LROW];
-    __shared__ __align__(16) uint16_t sb[2][LT * LROW];
-    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wm = wave / 2, wn = wave % 2;
-    uint32_t lid = blockIdx.x;
-    {
-        const uint32_t per = gridDim.x / 8;
-        if (lid < per * 8) lid = (lid % 8) * per + lid / 8;
-    }
-    const uint32_t ct = lid % nct, rt = (lid / nct) % nrt, ks = lid / (nct * nrt);
-    const uint64_t tr0 = (uint64_t)rt * LT;
-    const uint32_t tc0 = ct * LT;
-    const uint32_t kbeg = ks * kpiece;
-    const uint32_t kend = (kbeg + kpiece < dpad) ? kbeg + kpiece : dpad;
-
-    // this thread's pieces of each operand step: piece u = tid + 256 j covers
-    // tile row u / 8 (= tid / 8 + 32 j), k offset 8 * (tid % 8); pieces at or
-    // past kend (the last step of an odd number of 32-wide slices) are zero
-    const int kk = 8 * (tid % 8), rr = tid / 8;
-    const uint16_t *ga[LPC];
-    const uint16_t *gb[LPC];
-#pragma unroll
-    for (int j = 0; j < LPC; ++j) {
-        const uint64_t r = (tr0 + rr + 32 * j < n) ? tr0 + rr + 32 * j : n - 1;
-        const uint32_t c = (tc0 + rr + 32 * j < H) ? tc0 + rr + 32 * j : H - 1;
-        ga[j] = planes + r * ld + kk;
-        gb[j] = w + (uint64_t)c * dpad + kk;
-    }
-    const int so = rr * LROW + kk;
-    uint4 ra[LPC], rb[LPC];
-    auto fetch = [&](uint32_t k) {
-        const bool in = k + kk < kend;
-#pragma unroll
-        for (int j = 0; j < LPC; ++j) {
-            ra[j] = in ? *reinterpret_cast<const uint4 *>(ga[j] + k) : uint4{0u, 0u, 0u, 0u};
-            rb[j] = in ? *reinterpret_cast<const uint4 *>(gb[j] + k) : uint4{0u, 0u, 0u, 0u};
-        }
-    };
-    auto stage = [&](int buf) {
-#pragma unroll
-        for (int j = 0; j < LPC; ++j) {
-            *reinterpret_cast<uint4 *>(&sa[buf][so + 32 * j * LROW]) = ra[j];
-            *reinterpret_cast<uint4 *>(&sb[buf][so + 32 * j * LROW]) = rb[j];
-        }
-    };
-    fetch(kbeg);
-    stage(0);
-    __syncthreads();
-
-    f32x4 acc[4][4], prt[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-            prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-    const int lr = lane % 16, lk = (lane / 16) * 8;
-
-    for (uint32_t k0 = kbeg; k0 < kend; k0 += LK) {
-        const int cur = ((k0 - kbeg) / LK) & 1;
-        const bool more = k0 + LK < kend;
-        if (more) fetch(k0 + LK);
-        const uint16_t *ca = sa[cur];
-        const uint16_t *cb = sb[cur];
-#pragma unroll
-        for (int hs = 0; hs < LK / 32; ++hs) {
-            bf16x8 fa[4], fb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                fa[a] = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const uint4 *>(
-                                &ca[(wm * 64 + 16 * a + lr) * LROW + 32 * hs + lk]));
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                fb[b] = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const uint4 *>(
-                                &cb[(wn * 64 + 16 * b + lr) * LROW + 32 * hs + lk]));
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    prt[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], prt[a][b], 0, 0, 0);
-        }
-        if ((k0 + LK - kbeg) % LCHK == 0 || !more) {
-            // close the chunk: one fp32 addition per output
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[a][b][i] += prt[a][b][i];
-                    prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-        }
-        if (more) stage(cur ^ 1);
-        __syncthreads();
-    }
-
-    const uint64_t row0 = tr0 + (uint64_t)wm * 64;
-    const uint32_t col0 = tc0 + wn * 64;
-    if (part) {
-        // one k piece of several: its partial projections
-        float *pp = part + (uint64_t)ks * n * H;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t col = col0 + 16 * b + lr;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
-                    if (row < n && col < H) pp[row * H + col] = acc[a][b][i];
-                }
-        }
-        return;
-    }
-
-    // Epilogue: trusted sign bits and flags, 16 columns per ballot group.
-    unsigned long long flagged = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint32_t cbase = col0 + 16 * b;
-        if (cbase >= H) continue;
-        const uint32_t col = cbase + lr;
-        const float wn_ = (col < H) ? nw[col] : 0.f;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint64_t row = row0 + 16 * a + 4 * (lane / 16) + i;
-                const float xn = (row < n) ? nx[row] : 0.f;
-                const float v = acc[a][b][i];
-                if (proj && row < n && col < H) proj[row * H + col] = v;
-                const float tau = gamma * xn * wn_ + tau_abs;
-                const bool ok = (col < H) && (fabsf(v) > tau);
-                const bool bit = ok && (v > 0.f);
-                const bool flg = (col < H) && !ok;
-                const unsigned long long mb = __ballot(bit);
-                const unsigned long long mf = __ballot(flg);
-                if ((lane % 16) == 0 && row < n) {
-                    const int g = lane / 16;
-                    const uint64_t o = row * (2 * (uint64_t)Hw) + cbase / 16;
-                    bits16[o] = (uint16_t)(mb >> (16 * g));
-                    flags16[o] = (uint16_t)(mf >> (16 * g));
-                    flagged += __popcll((mf >> (16 * g)) & 0xFFFFull);
-                }
-            }
-        }
-    }
-    if ((lane % 16) == 0 && flagged) atomicAdd(nflag, flagged);
-}
-
-// Sum of the k pieces' partial projections, in piece order, then the same
-// certificate as the single-piece epilogue.  A thread takes one hyperplane of
-// RB consecutive rows; the 16 lanes 16j .. 16j+15 of a wavefront hold one
-// group of 16 hyperplanes (reads of consecutive hyperplanes are coalesced),
-// and each row's sign and flag words of the group come from two ballots.
-// Loads carry no branches (rows and hyperplanes are clamped into range, the
-// clamped values unused), so that they are in flight together.
-template <int RB>
-__global__ __launch_bounds__(256) void srp_finish_kernel(
-    const float *__restrict__ part, uint32_t ns, uint64_t n, uint64_t r0, uint32_t nr,
-    uint32_t H, uint32_t Hw, const float *__restrict__ nx, const float *__restrict__ nw,
-    float gamma, float tau_abs, uint16_t *__restrict__ bits16, uint16_t *__restrict__ flags16,
-    unsigned long long *__restrict__ nflag, float *__restrict__ proj) {
-    // rows r0 .. r0 + nr - 1; the thread count is below 2^31, so the
-    // indexing is 32-bit
-    const uint32_t G = (H + 15) / 16;
-    const int lane = threadIdx.x % 64;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t grp = t / 16;
-    const uint32_t rbk = grp / G;
-    const uint32_t g = grp - rbk * G, col = 16 * g + t % 16;
-    const uint32_t rl0 = rbk * RB;
-    const uint64_t pstride = n * H;
-    const uint32_t cc = col < H ? col : H - 1;
-    uint64_t ro[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) ro[r] = (r0 + (rl0 + r < nr ? rl0 + r : nr - 1)) * H + cc;
-    float v[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) v[r] = 0.f;
-    if (rl0 < nr) {
-        if constexpr (RB == 1) {
-#pragma unroll 8
-            for (uint32_t s = 0; s < ns; ++s) v[0] += part[(uint64_t)s * pstride + ro[0]];
-        } else {
-            for (uint32_t s = 0; s < ns; ++s) {
-                const float *ps = part + (uint64_t)s * pstride;
-#pragma unroll
-                for (int r = 0; r < RB; ++r) v[r] += ps[ro[r]];
-            }
-        }
-    }
-    unsigned long long nf = 0;
-    const float wn_ = nw[cc];
-    float xn[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) xn[r] = nx[r0 + (rl0 + r < nr ? rl0 + r : nr - 1)];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const uint32_t rl = rl0 + r;
-        const uint64_t row = r0 + rl;
-        bool bit = false, flg = false;
-        if (rl < nr && col < H) {
-            if (proj) proj[row * H + col] = v[r];
-            const float tau = gamma * xn[r] * wn_ + tau_abs;
-            const bool ok = fabsf(v[r]) > tau;
-            bit = ok && (v[r] > 0.f);
-            flg = !ok;
-        }
-        const unsigned long long mb = __ballot(bit);
-        const unsigned long long mf = __ballot(flg);
-        if (lane % 16 == 0 && rl < nr) {
-            const uint64_t o = row * (2 * (uint64_t)Hw) + g;
-            bits16[o] = (uint16_t)(mb >> lane);
-            flags16[o] = (uint16_t)(mf >> lane);
-        }
-        nf += (unsigned long long)__popcll(mf);
-    }
-    if (lane == 0 && nf) atomicAdd(nflag, nf);
-}
-
 // ---------------------------------------------------------------------------
 // Exact sign of sum_i x_i * w_i when FP64 cannot certify it.  Every product
 // is an exact double m * 2^e with |m| < 2^31 and e >= -151 (x: fp32/bf16,
@@ -578,7 +297,7 @@ __global__ __launch_bounds__(256) void srp_finish_kernel(
 // the products i = l, l + 64, ... into its own int64 digits, which are then
 // summed across the wavefront (no overflow for up to 2^30 terms in all), so
 // every lane returns the same sign.
-__device__ int exact_sign_wave(const void *xin, bool f32, uint64_t row, uint32_t d,
+__device__ int exact_sign_wave(const void *xin, bool f32, uint64_t row, uint32_t d, uint32_t ld,
                                const uint16_t *__restrict__ wh) {
     constexpr int NLIMB = 12;
     constexpr int BASE = -160;
@@ -586,8 +305,8 @@ __device__ int exact_sign_wave(const void *xin, bool f32, uint64_t row, uint32_t
 #pragma unroll
     for (int j = 0; j < NLIMB; ++j) limb[j] = 0;
     for (uint32_t i = threadIdx.x % 64; i < d; i += 64) {
-        const double xv = f32 ? (double)static_cast<const float *>(xin)[row * d + i]
-                              : (double)bf16_to_f32(static_cast<const uint16_t *>(xin)[row * d + i]);
+        const double xv = f32 ? (double)static_cast<const float *>(xin)[row * ld + i]
+                              : (double)bf16_to_f32(static_cast<const uint16_t *>(xin)[row * ld + i]);
         const double p = xv * (double)bf16_to_f32(wh[i]);
         if (p == 0.0) continue;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(p);
@@ -683,7 +402,7 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_kernel(
                 if (__builtin_amdgcn_readfirstlane(fabs(v) > 2.0 * (double)d * 0x1p-53 * a ? 1 : 0)) {
                     sgn = v > 0.0 ? 1 : -1;
                 } else {
-                    sgn = exact_sign_wave(xin, f32 != 0, row, d, wh);
+                    sgn = exact_sign_wave(xin, f32 != 0, row, d, d, wh);
                     if (lane == 0) atomicAdd(nexact, 1ull);
                 }
                 if (lane == 0) {
@@ -709,112 +428,401 @@ __global__ __launch_bounds__(256) void srp_recheck_pack_kernel(
     }
 }
 
-// Recheck + pack for bf16 rows read in place (d a multiple of 32, rows
-// 16-byte aligned).  One wavefront per row: its flagged hyperplanes are
-// listed in LDS, then recomputed one at a time across the wavefront, with
-// 16-byte loads of 8 bf16 values of the row and of the hyperplane and FP64
-// partial sums reduced across the lanes (one round of memory latency per
-// flagged projection).  Same certificate and exact fallback as
-// srp_recheck_pack_kernel.
-__global__ __launch_bounds__(256) void srp_recheck_pack_vec_kernel(
-    const uint16_t *__restrict__ x, uint64_t n, uint32_t d, const uint16_t *__restrict__ w,
-    const uint32_t *__restrict__ bits, const uint32_t *__restrict__ flags, uint32_t Hw,
-    uint32_t H, uint32_t K, uint32_t L, uint32_t *__restrict__ codes,
-    unsigned long long *__restrict__ nexact) {
-    extern __shared__ uint32_t sm[];
-    const int lane = threadIdx.x % 64;
-    const int wave = threadIdx.x / 64;
-    const uint64_t row = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave;
-    if (row >= n) return;
-    const uint32_t per_wave = Hw + (Hw * 32) / 2;  // bit words + uint16 flagged list
-    uint32_t *rb = sm + wave * per_wave;
-    uint16_t *fl = reinterpret_cast<uint16_t *>(rb + Hw);
-    for (uint32_t j = lane; j < Hw; j += 64) rb[j] = bits[row * Hw + j];
-    // list the flagged hyperplanes (wave prefix sums over flag words)
-    uint32_t nf = 0;
-    for (uint32_t j0 = 0; j0 < Hw; j0 += 64) {
-        const uint32_t j = j0 + lane;
-        uint32_t fw = (j < Hw) ? flags[row * Hw + j] : 0u;
-        const uint32_t c = (uint32_t)__popc(fw);
-        uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        uint32_t pos = nf + inc - c;
-        while (fw) {
-            const uint32_t b = (uint32_t)(__ffs(fw) - 1);
-            fw &= fw - 1;
-            fl[pos++] = (uint16_t)(j * 32 + b);
-        }
-        nf += (uint32_t)__shfl((int)inc, 63, 64);
+// The bf16 stage in one kernel: projection, sign certificate, FP64 recheck
+// of the flagged projections and packing of the codes.
+//
+// A workgroup takes a tile of TM = 16*MR rows against one group of whole
+// tables (gt consecutive tables, at most 48*NW hyperplanes), with NW*KS
+// wavefronts: column wavefront c owns the group's hyperplanes 48c .. 48c+47
+// (MR x 3 MFMA tiles of 16 x 16, v_mfma_f32_16x16x32_bf16), and each of the
+// KS k groups of NW wavefronts takes one contiguous run of whole 128-wide k
+// chunks.  A group walks its run in 64-wide steps: its rows are staged once
+// in LDS (double-buffered, rows padded by 16 bytes against bank conflicts)
+// and multiplied by its NW wavefronts, while each wavefront reads its own
+// hyperplanes' fragments straight from global memory (no other wavefront of
+// the group uses them; the hyperplanes of an index stay in L2); both are
+// prefetched one step ahead.  Each step waits on one round of memory
+// latency, so the KS groups (KS times the loads in flight, a chain of steps
+// KS times shorter) are what keeps a small grid busy.
+//
+// Accumulation is chunked: every 128 consecutive k accumulate into a fresh
+// partial (MFMA accumulate), the partials are added in fp32 within the
+// group, and the KS group sums are added in group order.  A product then
+// passes through at most 128 roundings inside its chunk (whatever order an
+// instruction sums its 32 products and its accumulator in), one per chunk of
+// its group and KS - 1 group additions.  With nch = ceil(d / 128) chunks,
+// cpg = ceil(nch / KS) per group and nch >= 2 KS, cpg + KS - 1 <= nch, so
+// |v32 - v| <= gamma_m * sum|x_i w_i| with m = min(128, d) + nch
+// (srp_lds_terms), far below the gamma_d of one long chain.
+//
+// The norms |x| are summed in FP64 from the staged pieces (squares of bf16
+// values are exact doubles, so they cannot underflow), per group and then
+// in group order.  Epilogue: trusted signs and flags become 16-bit words in
+// LDS by ballot; all wavefronts take the tile's rows in turn and recompute
+// each flagged projection in FP64 (8 bf16 values per lane per 16-byte load,
+// partials reduced by butterfly), certified when |v| > 2*d*2^-53*sum|x_i
+// w_i|, else by exact_sign_wave; then the codes of the group's tables are
+// written.
+//
+// Workgroup order: the hardware hands consecutive workgroup ids to the eight
+// XCDs in turn; ids are renumbered so that the groups of one row tile (which
+// read the same rows) run on one XCD, close in time, and share its L2.
+constexpr int LK = 64;        // k per pipeline step (two 32-wide MFMA slices)
+constexpr int LROW = LK + 8;  // bf16 per LDS row (16 bytes of padding)
+constexpr int LCHK = 128;     // k per accumulation chunk
+constexpr int FW = 48;        // hyperplanes per wavefront
+constexpr int FMAXW = 6;      // column wavefronts per workgroup at most
+constexpr int FMAXH = FW * FMAXW;  // hyperplanes per group at most
+constexpr int FWRD = FMAXH / 32;   // sign / flag words per row in LDS
+
+// Roundings a product passes through in srp_fused_kernel (see above).
+inline uint32_t srp_lds_terms(uint32_t dpad) {
+    return (dpad < (uint32_t)LCHK ? dpad : (uint32_t)LCHK) + (dpad + LCHK - 1) / LCHK;
+}
+
+// Sizes of one srp_fused_kernel variant.
+template <int MR, int NW, int KS>
+struct FusedShape {
+    static constexpr int TM = 16 * MR;
+    static constexpr int GT = 64 * NW;              // threads of one k group
+    static constexpr int XP = TM * LK / 8;          // 16-byte pieces of one step's rows
+    static constexpr int PPT = (XP + GT - 1) / GT;  // pieces per thread
+    static constexpr int XB = TM * LROW;            // bf16 per row buffer
+    static constexpr size_t XBYTES = (size_t)KS * 2 * XB * 2;
+    static constexpr size_t PBYTES = (size_t)(KS - 1) * TM * FW * NW * 4;  // group sums
+    static constexpr size_t LDS = XBYTES > PBYTES ? XBYTES : PBYTES;      // dynamic LDS
+};
+
+template <int MR, int NW, int KS>
+__global__ __launch_bounds__(64 * NW * KS) void srp_fused_kernel(
+    const uint16_t *__restrict__ x, uint32_t ld, uint32_t d, const uint16_t *__restrict__ w,
+    const uint16_t *__restrict__ wt, uint32_t dpad, const float *__restrict__ nw, uint64_t n,
+    uint32_t K, uint32_t L, uint32_t gt, float gamma, float tau_abs, uint32_t *__restrict__ codes,
+    unsigned long long *__restrict__ ctr, float *__restrict__ proj) {
+    using SH = FusedShape<MR, NW, KS>;
+    constexpr int TM = SH::TM, GT = SH::GT, XP = SH::XP, PPT = SH::PPT, XB = SH::XB;
+    constexpr int NWV = NW * KS;
+    // row buffers during the k loop, then the group sums (fp32)
+    extern __shared__ __align__(16) unsigned char dyn[];
+    uint16_t *sxa = reinterpret_cast<uint16_t *>(dyn);
+    float *part = reinterpret_cast<float *>(dyn);
+    __shared__ uint32_t sbits[TM * FWRD];
+    __shared__ uint32_t sflag[TM * FWRD];
+    __shared__ float snx[TM];
+    __shared__ double snx2[KS * TM];
+    uint16_t *sb16 = reinterpret_cast<uint16_t *>(sbits);
+    uint16_t *sf16 = reinterpret_cast<uint16_t *>(sflag);
+
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int cw = wave % NW, kg = wave / NW;  // column wavefront, k group
+    const int gtid = tid - kg * GT;            // thread within the k group
+    const uint32_t ng = (L + gt - 1) / gt;
+    uint32_t lid = blockIdx.x;
+    {
+        const uint32_t per = gridDim.x / 8;
+        if (lid < per * 8) lid = (lid % 8) * per + lid / 8;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // each flagged projection is recomputed by the whole wavefront: lane l
-    // takes the 8-value pieces l, l + 64, ... of the row and the hyperplane,
-    // all loads in flight at once
-    const uint16_t *xr = x + row * d;
-    for (uint32_t p = 0; p < nf; ++p) {
-        const uint32_t h = fl[p];
-        if (h >= H) continue;  // never: flags past H are zero
-        const uint16_t *wh = w + (uint64_t)h * d;
-        double v = 0.0, a = 0.0;
-#pragma unroll 8
-        for (uint32_t i = 8 * lane; i < d; i += 512) {
-            const uint4 xv = *reinterpret_cast<const uint4 *>(xr + i);
-            const uint4 wv = *reinterpret_cast<const uint4 *>(wh + i);
-            const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
-            const uint32_t ws[4] = {wv.x, wv.y, wv.z, wv.w};
+    const uint32_t rt = lid / ng, g = lid - rt * ng;
+    const uint64_t r0 = (uint64_t)rt * TM;
+    const uint32_t t0 = g * gt;
+    const uint32_t ntab = (L - t0 < gt) ? L - t0 : gt;
+    const uint32_t h0 = t0 * K, gcols = ntab * K, H = K * L;
+
+    // this group's k range (whole chunks) and step count; group 0 has the most
+    const uint32_t nch = (d + LCHK - 1) / LCHK, cpg = (nch + KS - 1) / KS;
+    const uint32_t c0 = (uint32_t)kg * cpg < nch ? (uint32_t)kg * cpg : nch;
+    const uint32_t kb = c0 * LCHK;
+    const uint32_t ke = (c0 + cpg) * LCHK < d ? (c0 + cpg) * LCHK : d;
+    const uint32_t nst = ke > kb ? (ke - kb + LK - 1) / LK : 0u;
+    const uint32_t kmax = cpg * LCHK < d ? cpg * LCHK : d;
+    const uint32_t nmax = (kmax + LK - 1) / LK;
+
+    // this thread's pieces of the rows: piece p covers tile row p / 8, k
+    // offset 8 * (p % 8) of the step (rows past n clamped, never output)
+    const uint16_t *xp[PPT];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const double x0 = (double)__uint_as_float(xs[e] << 16);
-                const double x1 = (double)__uint_as_float(xs[e] & 0xFFFF0000u);
-                const double w0 = (double)__uint_as_float(ws[e] << 16);
-                const double w1 = (double)__uint_as_float(ws[e] & 0xFFFF0000u);
-                const double p0_ = x0 * w0, p1_ = x1 * w1;
-                v += p0_;
-                v += p1_;
-                a += fabs(p0_);
-                a += fabs(p1_);
+    for (int j = 0; j < PPT; ++j) {
+        const uint32_t p = gtid + GT * j;
+        const uint64_t r = (p < XP && r0 + p / 8 < n) ? r0 + p / 8 : n - 1;
+        xp[j] = x + r * ld + 8 * (p % 8);
+    }
+    // this lane's hyperplanes: column 16b + lane % 16 of the wavefront's 48
+    // (clamped into the group; the clamped columns' outputs are unused), read
+    // from the tiled copy, where a fragment (16 hyperplanes x 32 k) is 1 KB
+    // contiguous: the next 32 k lie 512 values further
+    const int lr = lane % 16, lk = (lane / 16) * 8;
+    const uint16_t *wp[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const uint32_t hr = FW * cw + 16 * b + lr;
+        const uint32_t c = h0 + (hr < gcols ? hr : gcols - 1);
+        wp[b] = wt + (uint64_t)(c / 16) * (dpad / 32) * 512 + (c % 16) * 32 + lk;
+    }
+    uint16_t *sx = sxa + kg * 2 * XB;  // this group's two row buffers
+
+    uint4 xr[PPT];
+    uint4 wf[2][3], wn[2][3];
+    double ss[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) ss[j] = 0.0;
+    auto fetch_x = [&](uint32_t k0) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const uint32_t p = gtid + GT * j;
+            const bool in = p < XP && k0 + 8 * (p % 8) < ke;
+            xr[j] = in ? *reinterpret_cast<const uint4 *>(xp[j] + k0) : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto fetch_w = [&](uint32_t k0, uint4(&f)[2][3]) {
+#pragma unroll
+        for (int hs = 0; hs < 2; ++hs) {
+            const bool in = k0 + 32 * hs < ke;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                f[hs][b] = in ? *reinterpret_cast<const uint4 *>(wp[b] + (k0 / 32 + hs) * 512)
+                              : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const uint32_t p = gtid + GT * j;
+            if (p < XP) {
+                *reinterpret_cast<uint4 *>(&sx[buf * XB + (p / 8) * LROW + 8 * (p % 8)]) = xr[j];
+                const uint32_t v[4] = {xr[j].x, xr[j].y, xr[j].z, xr[j].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double lo = (double)__uint_as_float(v[e] << 16);
+                    const double hi = (double)__uint_as_float(v[e] & 0xFFFF0000u);
+                    ss[j] += lo * lo + hi * hi;
+                }
             }
         }
-        v = wave_sum_f64(v);
-        a = wave_sum_f64(a);
-        int sgn;
-        // the butterfly sums are bit-identical in every lane; lane 0's
-        // verdict keeps the branch uniform by construction
-        if (__builtin_amdgcn_readfirstlane(fabs(v) > 2.0 * (double)d * 0x1p-53 * a ? 1 : 0)) {
-            sgn = v > 0.0 ? 1 : -1;
-        } else {
-            sgn = exact_sign_wave(x, false, row, d, wh);
-            if (lane == 0) atomicAdd(nexact, 1ull);
+    };
+
+    if (nst > 0) {
+        fetch_x(kb);
+        fetch_w(kb, wf);
+        stage(0);
+    }
+    __syncthreads();
+
+    f32x4 acc[MR][3], prt[MR][3];
+#pragma unroll
+    for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-        if (lane == 0) {
-            const uint32_t m = 1u << (h & 31);
-            if (sgn > 0)
-                atomicOr(&rb[h >> 5], m);
-            else
-                atomicAnd(&rb[h >> 5], ~m);
+    for (uint32_t st = 0; st < nmax; ++st) {
+        // every group passes every barrier; a group past its last step idles
+        const bool act = st < nst;
+        const bool more = st + 1 < nst;
+        const uint32_t k0 = kb + st * LK;
+        if (more) {
+            fetch_x(k0 + LK);
+            fetch_w(k0 + LK, wn);
+        }
+        if (act) {
+            const uint16_t *cx = sx + (st & 1) * XB;
+#pragma unroll
+            for (int hs = 0; hs < 2; ++hs) {
+                if (k0 + 32 * hs < ke) {  // uniform: ke is a multiple of 32
+                    bf16x8 fa[MR];
+#pragma unroll
+                    for (int a = 0; a < MR; ++a)
+                        fa[a] = __builtin_bit_cast(
+                            bf16x8,
+                            *reinterpret_cast<const uint4 *>(&cx[(16 * a + lr) * LROW + 32 * hs + lk]));
+#pragma unroll
+                    for (int a = 0; a < MR; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+                            prt[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                fa[a], __builtin_bit_cast(bf16x8, wf[hs][b]), prt[a][b], 0, 0, 0);
+                }
+            }
+            if ((k0 + LK - kb) % LCHK == 0 || !more) {
+                // close the chunk: one fp32 addition per output
+#pragma unroll
+                for (int a = 0; a < MR; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[a][b][i] += prt[a][b][i];
+                        prt[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+        }
+        if (more) {
+            stage((st + 1) & 1);
+#pragma unroll
+            for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) wf[hs][b] = wn[hs][b];
+        }
+        __syncthreads();
+    }
+
+    // row norms: the 8 lanes holding one row's pieces are adjacent; the
+    // groups' sums are added in group order
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        double v = ss[j];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        const uint32_t p = gtid + GT * j;
+        if (p < XP && p % 8 == 0) snx2[kg * TM + p / 8] = v;
+    }
+    // the group sums (the row buffers are free: every group left the loop)
+    if (KS > 1 && kg > 0) {
+        float *pp = part + (size_t)(kg - 1) * TM * FW * NW + (size_t)cw * MR * 3 * 4 * 64;
+#pragma unroll
+        for (int a = 0; a < MR; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pp[((a * 3 + b) * 4 + i) * 64 + lane] = acc[a][b][i];
+    }
+    __syncthreads();
+    if (tid < TM) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) v += snx2[q * TM + tid];
+        snx[tid] = (float)sqrt(v);
+    }
+    if (KS > 1 && kg == 0) {
+#pragma unroll
+        for (int q = 1; q < KS; ++q) {
+            const float *pp = part + (size_t)(q - 1) * TM * FW * NW + (size_t)cw * MR * 3 * 4 * 64;
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[a][b][i] += pp[((a * 3 + b) * 4 + i) * 64 + lane];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t t = lane; t < L; t += 64) {
-        const uint32_t b0 = t * K;
-        const uint32_t wi = b0 / 32, sh = b0 % 32;
-        uint64_t vv = rb[wi];
-        if (sh + K > 32 && wi + 1 < Hw) vv |= (uint64_t)rb[wi + 1] << 32;
-        codes[row * L + t] = (uint32_t)((vv >> sh) & ((K >= 32) ? 0xFFFFFFFFull : ((1ull << K) - 1)));
+    __syncthreads();
+
+    // trusted signs and flags (group 0), 16 hyperplanes per ballot group
+    if (kg == 0) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const uint32_t hr = FW * cw + 16 * b + lr;
+            const bool cv = hr < gcols;
+            const float wn_ = nw[h0 + (cv ? hr : 0u)];
+#pragma unroll
+            for (int a = 0; a < MR; ++a) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t rl = 16 * a + 4 * (lane / 16) + i;
+                    const float v = acc[a][b][i];
+                    if (proj && cv && r0 + rl < n) proj[(r0 + rl) * H + h0 + hr] = v;
+                    const float tau = gamma * snx[rl] * wn_ + tau_abs;
+                    const bool ok = cv && fabsf(v) > tau;
+                    const unsigned long long mb = __ballot(ok && v > 0.f);
+                    const unsigned long long mf = __ballot(cv && !ok);
+                    if (lr == 0) {
+                        const int q = lane / 16;
+                        sb16[rl * 2 * FWRD + 3 * cw + b] = (uint16_t)(mb >> (16 * q));
+                        sf16[rl * 2 * FWRD + 3 * cw + b] = (uint16_t)(mf >> (16 * q));
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // recheck: wavefront w takes rows w, w + NW*KS, ...; a row's sign words
+    // are changed by its wavefront's lane 0 only
+    const uint32_t nrow = (n - r0 < (uint64_t)TM) ? (uint32_t)(n - r0) : (uint32_t)TM;
+    const uint32_t gw = (gcols + 31) / 32;
+    unsigned long long nflag = 0, nexact = 0;
+    for (uint32_t rl = wave; rl < nrow; rl += NWV) {
+        // only the group's gcols bits: the ballots leave the upper half of
+        // the last word unwritten when gcols / 16 is odd
+        uint32_t fw = 0u;
+        if ((uint32_t)lane < gw) {
+            fw = sflag[rl * FWRD + lane];
+            const uint32_t nb = gcols - 32u * (uint32_t)lane;
+            if (nb < 32u) fw &= (1u << nb) - 1u;
+        }
+        unsigned long long any = __ballot(fw != 0);
+        const uint16_t *xrow = x + (r0 + rl) * ld;
+        while (any) {
+            const int src = __ffsll((long long)any) - 1;
+            any &= any - 1;
+            uint32_t word = (uint32_t)__shfl((int)fw, src, 64);
+            while (word) {
+                const int bit = __ffs(word) - 1;
+                word &= word - 1;
+                const uint32_t hr = (uint32_t)src * 32 + bit;
+                const uint16_t *wh = w + (uint64_t)(h0 + hr) * dpad;
+                double v = 0.0, a = 0.0;
+#pragma unroll 8
+                for (uint32_t i = 8 * lane; i < d; i += 512) {
+                    const uint4 xv = *reinterpret_cast<const uint4 *>(xrow + i);
+                    const uint4 wv = *reinterpret_cast<const uint4 *>(wh + i);
+                    const uint32_t xs4[4] = {xv.x, xv.y, xv.z, xv.w};
+                    const uint32_t ws4[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double x0 = (double)__uint_as_float(xs4[e] << 16);
+                        const double x1 = (double)__uint_as_float(xs4[e] & 0xFFFF0000u);
+                        const double w0 = (double)__uint_as_float(ws4[e] << 16);
+                        const double w1 = (double)__uint_as_float(ws4[e] & 0xFFFF0000u);
+                        const double p0 = x0 * w0, p1 = x1 * w1;
+                        v += p0;
+                        v += p1;
+                        a += fabs(p0);
+                        a += fabs(p1);
+                    }
+                }
+                v = wave_sum_f64(v);
+                a = wave_sum_f64(a);
+                int sgn;
+                // the butterfly sums are bit-identical in every lane; lane
+                // 0's verdict keeps the branch uniform by construction
+                if (__builtin_amdgcn_readfirstlane(fabs(v) > 2.0 * (double)d * 0x1p-53 * a ? 1 : 0)) {
+                    sgn = v > 0.0 ? 1 : -1;
+                } else {
+                    sgn = exact_sign_wave(x, false, r0 + rl, d, ld, wh);
+                    ++nexact;
+                }
+                if (lane == 0) {
+                    const uint32_t m = 1u << bit;
+                    if (sgn > 0)
+                        sbits[rl * FWRD + src] |= m;
+                    else
+                        sbits[rl * FWRD + src] &= ~m;
+                }
+                ++nflag;
+            }
+        }
+    }
+    if (ctr && lane == 0) {
+        if (nflag) atomicAdd(&ctr[0], nflag);
+        if (nexact) atomicAdd(&ctr[1], nexact);
+    }
+    __syncthreads();
+
+    // codes of the group's tables (K <= 24 bits, within two words)
+    for (uint32_t idx = tid; idx < nrow * ntab; idx += 64 * NWV) {
+        const uint32_t rl = idx / ntab, t = idx - rl * ntab;
+        const uint32_t b0 = t * K, wi = b0 / 32, sh = b0 % 32;
+        uint64_t v = sbits[rl * FWRD + wi];
+        if (sh + K > 32) v |= (uint64_t)sbits[rl * FWRD + wi + 1] << 32;
+        codes[(r0 + rl) * L + t0 + t] = (uint32_t)((v >> sh) & ((1ull << K) - 1));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Roundings a product can pass through: one long chain of 3 * dpad terms for
-// the fp32 kernel (three bf16 planes); chunked for the LDS kernel (bf16).
+// the fp32 kernel (three bf16 planes); chunked for the fused kernel (bf16).
 // gamma_m = m u / (1 - m u) with u = 2^-23, widened by 2^-6 for the fp32
 // rounding of the two norms and of gamma itself; the absolute term covers
 // products and partial sums that the matrix cores flush below 2^-126.
@@ -834,17 +842,147 @@ static bool srp_inplace(const Index &ix, const void *xdev) {
            (reinterpret_cast<uintptr_t>(xdev) & 15) == 0;
 }
 
-size_t srp_scratch_bytes(const Index &ix, uint64_t n, const void *xdev) {
-    const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
-    const int nsplit = ix.p.family == FLINNG_SRP_F32 ? 3 : 1;
-    const bool planes = !(xdev && srp_inplace(ix, xdev));
-    size_t partial = 0;
-    if (nsplit == 1) {
-        const SrpSplit sp = srp_split(ix.p.K * ix.p.L, n, ix.dpad);
-        if (sp.ns > 1) partial = Arena::round((size_t)sp.ns * n * ix.p.K * ix.p.L * 4);
+// How srp_fused_kernel covers n rows: MR (tile rows / 16), NW (column
+// wavefronts), KS (k groups) and gt (tables per group), from a model fitted
+// to kernel times on MI355X (ReLU embeddings, d = 4096, K*L = 288, batches of
+// 128 to 10,000 rows; every plan within 15% of the best one measured).  A
+// workgroup takes steps = 2 ceil(nch / KS) 64-wide steps, each about
+// 0.2 us + 0.25 us per KB that one wavefront loads in it (its share of the
+// rows and its 48 hyperplanes: TM / (8 NW) + 6 KB): memory latency and the
+// wavefront's own load throughput.  Workgroups run in rounds of 256 times
+// the number a compute unit holds (8, 12 or 16 wavefronts for MR = 4, 2, 1),
+// and the whole grid's loads take at least their bytes at 10 TB/s; plus a
+// fixed 2 us.  KS needs nch >= 2 KS (the rounding bound).
+struct SrpPlan {
+    int mr, nw, ks;
+    uint32_t gt;
+    uint64_t wgs;
+};
+
+// The compiled variants: KS = 8 only with one column wavefront and tiles of
+// at most 32 rows (the row buffers of 8 groups).
+static bool srp_variant(int mr, int nw, int ks) {
+    return ks == 1 || (ks == 2 && nw <= 4) || (ks == 4 && nw <= 2) || (ks == 8 && nw == 1 && mr <= 2);
+}
+
+static SrpPlan srp_plan(uint32_t K, uint32_t L, uint64_t n, uint32_t d) {
+    static const int NWS[] = {1, 2, 3, 4, 6};
+    static const int MRS[] = {1, 2, 4};
+    static const int KSS[] = {1, 2, 4, 8};
+    const double A = 0.2e-6, B = 0.25e-6, BWG = 10e12, FIX = 2e-6;
+    const uint32_t nch = (d + LCHK - 1) / LCHK;
+    SrpPlan best{4, FMAXW, 1, 1, 0};
+    double best_t = -1.0;
+    for (int mr : MRS) {
+        const uint64_t tm = 16 * (uint64_t)mr, nrt = (n + tm - 1) / tm;
+        const int wcu = mr == 4 ? 8 : (mr == 2 ? 12 : 16);
+        for (uint32_t ng = 1; ng <= L; ++ng) {
+            const uint32_t gt = (L + ng - 1) / ng;
+            if ((L + gt - 1) / gt != ng || gt * K > (uint32_t)FMAXH) continue;
+            const uint32_t need = (gt * K + FW - 1) / FW;
+            int nw = FMAXW;
+            for (int c : NWS)
+                if ((uint32_t)c >= need) {
+                    nw = c;
+                    break;
+                }
+            for (int ks : KSS) {
+                if (!srp_variant(mr, nw, ks) || (ks > 1 && nch < 2u * ks)) continue;
+                const uint64_t wgs = nrt * ng;
+                const double steps = 2.0 * ((nch + ks - 1) / ks);
+                const double kbw = (double)tm / (8.0 * nw) + 6.0;
+                const uint64_t occ = (uint64_t)std::max(1, wcu / (nw * ks));
+                const double rounds = (double)((wgs + 256 * occ - 1) / (256 * occ));
+                const double bytes = (double)wgs * ks * steps * (double)(tm + FW * nw) * 128.0;
+                const double t = std::max(rounds * steps * (A + B * kbw), bytes / BWG) + FIX;
+                if (best_t < 0.0 || t < best_t || (t == best_t && wgs < best.wgs)) {
+                    best = SrpPlan{mr, nw, ks, gt, wgs};
+                    best_t = t;
+                }
+            }
+        }
     }
-    return (planes ? Arena::round((size_t)nsplit * n * ix.dpad * 2) : 0) + Arena::round(n * 4) +
-           2 * Arena::round(n * Hw * 4) + Arena::round(16) + partial;
+    return best;
+}
+
+struct SrpFusedArgs {
+    const uint16_t *x;
+    uint32_t ld, d;
+    const Index *ix;
+    uint64_t n;
+    float gamma, tau_abs;
+    uint32_t *codes;
+    unsigned long long *ctr;
+    float *proj;
+};
+
+template <int MR, int NW, int KS>
+static void srp_launch(const SrpPlan &pl, const SrpFusedArgs &a, hipStream_t s) {
+    constexpr size_t lds = FusedShape<MR, NW, KS>::LDS;
+    // once per variant and process (a throwing initialiser is retried)
+    static const bool attrs_ok = [] {
+        const void *fn = reinterpret_cast<const void *>(&srp_fused_kernel<MR, NW, KS>);
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            fail(FLINNG_EDEVICE, "SRP kernel: its LDS does not fit");
+        return true;
+    }();
+    (void)attrs_ok;
+    hipLaunchKernelGGL((srp_fused_kernel<MR, NW, KS>), dim3((unsigned)pl.wgs), dim3(64 * NW * KS),
+                       lds, s, a.x, a.ld, a.d, a.ix->hyp, a.ix->hypt, a.ix->dpad, a.ix->hypnorm, a.n,
+                       a.ix->p.K, a.ix->p.L, pl.gt, a.gamma, a.tau_abs, a.codes, a.ctr, a.proj);
+}
+
+template <int MR, int KS>
+static void srp_launch_nw(const SrpPlan &pl, const SrpFusedArgs &a, hipStream_t s) {
+    if constexpr (KS == 1) {
+        switch (pl.nw) {
+            case 1: srp_launch<MR, 1, 1>(pl, a, s); break;
+            case 2: srp_launch<MR, 2, 1>(pl, a, s); break;
+            case 3: srp_launch<MR, 3, 1>(pl, a, s); break;
+            case 4: srp_launch<MR, 4, 1>(pl, a, s); break;
+            default: srp_launch<MR, 6, 1>(pl, a, s); break;
+        }
+    } else if constexpr (KS == 2) {
+        switch (pl.nw) {
+            case 1: srp_launch<MR, 1, 2>(pl, a, s); break;
+            case 2: srp_launch<MR, 2, 2>(pl, a, s); break;
+            case 3: srp_launch<MR, 3, 2>(pl, a, s); break;
+            default: srp_launch<MR, 4, 2>(pl, a, s); break;
+        }
+    } else if constexpr (KS == 4) {
+        if (pl.nw == 1)
+            srp_launch<MR, 1, 4>(pl, a, s);
+        else
+            srp_launch<MR, 2, 4>(pl, a, s);
+    } else if constexpr (MR <= 2) {
+        srp_launch<MR, 1, 8>(pl, a, s);
+    } else {
+        fail(FLINNG_EDEVICE, "internal: no SRP kernel variant for the plan");
+    }
+}
+
+template <int MR>
+static void srp_launch_ks(const SrpPlan &pl, const SrpFusedArgs &a, hipStream_t s) {
+    switch (pl.ks) {
+        case 1: srp_launch_nw<MR, 1>(pl, a, s); break;
+        case 2: srp_launch_nw<MR, 2>(pl, a, s); break;
+        case 4: srp_launch_nw<MR, 4>(pl, a, s); break;
+        default: srp_launch_nw<MR, 8>(pl, a, s); break;
+    }
+}
+
+__global__ void srp_zero_ctr_kernel(unsigned long long *ctr) {
+    if (threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
+}
+
+size_t srp_scratch_bytes(const Index &ix, uint64_t n, const void *xdev) {
+    const bool planes = !(xdev && srp_inplace(ix, xdev));
+    if (ix.p.family != FLINNG_SRP_F32)
+        return (planes ? Arena::round((size_t)n * ix.dpad * 2) : 0) + Arena::round(16);
+    const uint64_t Hw = ((uint64_t)ix.p.K * ix.p.L + 31) / 32;
+    return Arena::round((size_t)3 * n * ix.dpad * 2) + Arena::round(n * 4) +
+           2 * Arena::round(n * Hw * 4) + Arena::round(16);
 }
 
 void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipStream_t s,
@@ -855,7 +993,6 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
     const uint32_t K = ix.p.K, L = ix.p.L, H = K * L;
     const uint32_t Hw = (H + 31) / 32;
     const bool f32 = ix.p.family == FLINNG_SRP_F32;
-    const int nsplit = f32 ? 3 : 1;
     Scratch sc(ws, s);
 
     // stage values on the device (host inputs never come with an arena)
@@ -867,88 +1004,67 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         FL_HIP(hipMemcpyAsync(xcopy.ptr, in.values, n * d * esz, hipMemcpyHostToDevice, s));
         xdev = xcopy.ptr;
     }
-    const bool inplace = srp_inplace(ix, xdev);
-    uint16_t *planes = sc.get<uint16_t>(inplace ? 0 : (size_t)nsplit * n * dpad * 2);
-    float *nx = sc.get<float>(n * 4);
-    uint32_t *bits = sc.get<uint32_t>(n * Hw * 4);
-    uint32_t *flags = sc.get<uint32_t>(n * Hw * 4);
-    unsigned long long *ctr = sc.get<unsigned long long>(16);
-    // bf16 rows: the LDS kernel, with k split into pieces for small batches
-    SrpSplit sp{};
-    float *part = nullptr;
-    if (nsplit == 1) {
-        sp = srp_split(H, n, dpad);
-        if ((uint64_t)sp.nct * sp.nrt * sp.ns > 0x7FFFFFFFull)
-            fail(FLINNG_EINVAL, "SRP batch too large for one launch");
-        if (sp.ns > 1) part = sc.get<float>((size_t)sp.ns * n * H * 4);
-    }
-    {
-        dim3 grid((unsigned)((n + 3) / 4));
-        if (f32)
-            hipLaunchKernelGGL(prep_kernel<true>, grid, dim3(256), 0, s, xdev, n, d, dpad, planes,
-                               nx, bits, flags, Hw, ctr);
-        else
-            hipLaunchKernelGGL(prep_kernel<false>, grid, dim3(256), 0, s, xdev, n, d, dpad,
-                               inplace ? nullptr : planes, nx, bits, flags, Hw, ctr);
-        FL_CHECK_LAUNCH();
-    }
-    const uint16_t *pl = inplace ? static_cast<const uint16_t *>(xdev) : planes;
-    const uint32_t ld = inplace ? d : dpad;
-    const uint64_t pstride = (uint64_t)n * dpad;
-
     double gam = 0.0, tabs = 0.0;
     srp_bound(ix, &gam, &tabs);
     const float gamma = (float)gam;
     const float tau_abs = (float)tabs;
 
+    if (!f32) {
+        // bf16 rows: one fused kernel, on the rows in place or on a padded
+        // copy (zeros past d, which add nothing to any sum)
+        const bool inplace = srp_inplace(ix, xdev);
+        uint16_t *planes = sc.get<uint16_t>(inplace ? 0 : (size_t)n * dpad * 2);
+        unsigned long long *ctr = sc.get<unsigned long long>(16);
+        if (counters_host) {
+            hipLaunchKernelGGL(srp_zero_ctr_kernel, dim3(1), dim3(64), 0, s, ctr);
+            FL_CHECK_LAUNCH();
+        }
+        if (!inplace) {
+            hipLaunchKernelGGL(prep_kernel<false>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s,
+                               xdev, n, d, dpad, planes, nullptr, nullptr, nullptr, 0u, nullptr);
+            FL_CHECK_LAUNCH();
+        }
+        const SrpPlan pl = srp_plan(K, L, n, dpad);
+        if (pl.wgs > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "SRP batch too large for one launch");
+        const SrpFusedArgs a{inplace ? static_cast<const uint16_t *>(xdev) : planes,
+                             dpad, dpad, &ix, n, gamma, tau_abs, codes_dev,
+                             counters_host ? ctr : nullptr, proj_dev};
+        switch (pl.mr) {
+            case 1: srp_launch_ks<1>(pl, a, s); break;
+            case 2: srp_launch_ks<2>(pl, a, s); break;
+            default: srp_launch_ks<4>(pl, a, s); break;
+        }
+        FL_CHECK_LAUNCH();
+        if (counters_host) {
+            unsigned long long c[2];
+            FL_HIP(hipMemcpyAsync(c, ctr, 16, hipMemcpyDeviceToHost, s));
+            FL_HIP(hipStreamSynchronize(s));
+            counters_host[0] = c[0];
+            counters_host[1] = c[1];
+        }
+        return;
+    }
+
+    // fp32 rows: three bf16 planes, srp_mfma_kernel, then recheck + pack
+    uint16_t *planes = sc.get<uint16_t>((size_t)3 * n * dpad * 2);
+    float *nx = sc.get<float>(n * 4);
+    uint32_t *bits = sc.get<uint32_t>(n * Hw * 4);
+    uint32_t *flags = sc.get<uint32_t>(n * Hw * 4);
+    unsigned long long *ctr = sc.get<unsigned long long>(16);
+    hipLaunchKernelGGL(prep_kernel<true>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, xdev, n,
+                       d, dpad, planes, nx, bits, flags, Hw, ctr);
+    FL_CHECK_LAUNCH();
     constexpr int MR = 4, NR = 4, WM = 2, WN = 2;
     dim3 grid((H + 16 * NR * WN - 1) / (16 * NR * WN),
               (unsigned)((n + 16 * MR * WM - 1) / (16 * MR * WM)));
-    unsigned long long *nflag = ctr;
-    if (nsplit == 3)
-        hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 3>), grid, dim3(64 * WM * WN), 0, s,
-                           pl, pstride, ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs,
-                           reinterpret_cast<uint16_t *>(bits), reinterpret_cast<uint16_t *>(flags),
-                           nflag, proj_dev);
-    else {
-        hipLaunchKernelGGL(srp_mfma_lds_kernel, dim3(sp.nct * sp.nrt * sp.ns), dim3(256), 0, s, pl,
-                           ld, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw, gamma, tau_abs, sp.nct,
-                           sp.nrt, sp.kpiece, part, reinterpret_cast<uint16_t *>(bits),
-                           reinterpret_cast<uint16_t *>(flags), nflag, part ? nullptr : proj_dev);
-        if (part) {
-            FL_CHECK_LAUNCH();
-            // rows per thread: RB * ns loads in flight
-            const int rb = sp.ns >= 8 ? 1 : 4;
-            const uint64_t per_rb = (uint64_t)((H + 15) / 16) * 16;
-            const uint64_t rows_max = ((1ull << 30) / per_rb) * rb;
-            uint16_t *b16 = reinterpret_cast<uint16_t *>(bits);
-            uint16_t *f16 = reinterpret_cast<uint16_t *>(flags);
-            for (uint64_t r0 = 0; r0 < n; r0 += rows_max) {
-                const uint32_t nr = (uint32_t)std::min<uint64_t>(rows_max, n - r0);
-                const uint64_t nt = (nr + rb - 1) / rb * per_rb;
-                const dim3 g((unsigned)((nt + 255) / 256));
-                if (rb == 1)
-                    hipLaunchKernelGGL(srp_finish_kernel<1>, g, dim3(256), 0, s, part, sp.ns, n, r0,
-                                       nr, H, Hw, nx, ix.hypnorm, gamma, tau_abs, b16, f16, nflag,
-                                       proj_dev);
-                else
-                    hipLaunchKernelGGL(srp_finish_kernel<4>, g, dim3(256), 0, s, part, sp.ns, n, r0,
-                                       nr, H, Hw, nx, ix.hypnorm, gamma, tau_abs, b16, f16, nflag,
-                                       proj_dev);
-                FL_CHECK_LAUNCH();
-            }
-        }
-    }
+    hipLaunchKernelGGL((srp_mfma_kernel<MR, NR, WM, WN, 3>), grid, dim3(64 * WM * WN), 0, s,
+                       planes, (uint64_t)n * dpad, dpad, ix.hyp, dpad, nx, ix.hypnorm, n, H, Hw,
+                       gamma, tau_abs, reinterpret_cast<uint16_t *>(bits),
+                       reinterpret_cast<uint16_t *>(flags), ctr, proj_dev);
     FL_CHECK_LAUNCH();
-    if (inplace)
-        hipLaunchKernelGGL(srp_recheck_pack_vec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
-                           4 * (Hw + Hw * 16) * sizeof(uint32_t), s,
-                           static_cast<const uint16_t *>(xdev), n, d, ix.hyp, bits, flags, Hw, H,
-                           K, L, codes_dev, nflag + 1);
-    else
-        hipLaunchKernelGGL(srp_recheck_pack_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
-                           4 * Hw * sizeof(uint32_t), s, xdev, (int)f32, n, d, ix.hyp, dpad, bits,
-                           flags, Hw, H, K, L, codes_dev, nflag + 1);
+    hipLaunchKernelGGL(srp_recheck_pack_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256),
+                       4 * Hw * sizeof(uint32_t), s, xdev, 1, n, d, ix.hyp, dpad, bits, flags, Hw,
+                       H, K, L, codes_dev, ctr + 1);
     FL_CHECK_LAUNCH();
     if (counters_host) {
         unsigned long long c[2];

@@ -98,6 +98,37 @@ def _cancelling_rows(w, rng, nrand, boost=2.0**6, tiny=2.0**-20):
     return np.stack(rows)
 
 
+@pytest.mark.parametrize("n,d,K,L", [(2048, 4096, 24, 12), (3000, 256, 16, 7), (4000, 512, 24, 12),
+                                     (700, 96, 24, 5), (600, 100, 24, 5), (1500, 64, 3, 33)])
+def test_srp_bf16_rechecks_only_near_zero(fl, n, d, K, L):
+    """bf16 rows with no projection near zero (Gaussian rows): the projection
+    stage may flag only projections within its error bound of zero, so every
+    flagged one has |v| <= tau + gamma |x| |w| (v the exact value, tau =
+    gamma |x| |w| + tau_abs), and only those FP64 cannot certify take the
+    exact-sum fallback.  Flags
+    outside the hyperplanes a workgroup covers (hyperplane groups whose count
+    is an odd number of 16) would show up as extra rechecks and exact sums."""
+    log("srp bf16 recheck count", n, d, K, L)
+    rng = np.random.default_rng(n + 7 * d + K)
+    x = synth.f32_to_bf16(rng.standard_normal((n, d)).astype(np.float32))
+    gi = fl.Index(x, 1, K, L, 2, max(1, n // 4), seed=99)
+    w = oracle.hyperplanes(99, K * L, d)
+    xd = oracle.bf16_to_f64(x)
+    v = xd @ w.T
+    _, (gam, tabs) = gi.debug_projections(x[:1])
+    tau = gam * np.sqrt((xd * xd).sum(1))[:, None] * np.sqrt((w * w).sum(1))[None, :] + tabs
+    near = int((np.abs(v) <= 2.1 * tau).sum())
+    # FP64 certifies a sign unless |v| <= 2 d 2^-53 sum|x_i w_i| (exact zeros
+    # among them): only those may take the exact sum
+    uncert = int((np.abs(v) <= 2 * d * 2.0**-53 * (np.abs(xd) @ np.abs(w).T)).sum())
+    log("rechecked", gi.info.srp_rechecked, "exact", gi.info.srp_exact, "near zero", near,
+        "uncertifiable", uncert)
+    assert gi.info.srp_exact <= uncert
+    assert gi.info.srp_rechecked <= near
+    m = min(n, 400)
+    assert np.array_equal(gi.debug_hash(x[:m]), oracle.srp_codes(xd[:m], 99, K, L, w=w))
+
+
 @pytest.mark.parametrize("family,d", [(0, 64), (0, 100), (1, 128), (1, 100)])
 def test_srp_extreme_scales_and_cancellations(fl, family, d):
     """Rows scaled by 2^0, 2^-70, 2^-80 and 2^-100 (fp32 sums of their

@@ -262,13 +262,13 @@ def stages(w, torch, fl, steps, persistent, out):
             "passes": st[3], "rows_gathered_final": st[4], "touched_bytes_per_launch": int(touched)}
     out = {"hash_ms": hash_ms, "decode_ms": decode_ms, "query_roofline": roof}
     if w.dense:
-        # the hash stage (norms, bf16 MFMA projection, FP64 recheck, pack)
-        # against the dense bf16 matrix-core peak: a lower bound on the
-        # projection kernel's own utilisation
+        # the hash stage (one srp_fused_kernel launch: norms, bf16 MFMA
+        # projection, FP64 recheck, pack) against the dense bf16 matrix-core
+        # peak
         flops = 2.0 * w.nq * w.cfg["d"] * w.K * w.L
         tf = flops / (hash_ms / 1e3) / 1e12
         out["hash_roofline"] = {
-            "kernel": "SRP hash stage (prep + srp_mfma_lds_kernel + recheck/pack)",
+            "kernel": "SRP hash stage (srp_fused_kernel: projection + certificate + recheck + pack)",
             "workload": w.name, "K": w.K, "L": w.L, "bound": "mfma", "achieved": round(tf, 2),
             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 4),
             "alg_flops_per_launch": flops, "launch_ms": round(hash_ms, 4), "traffic": None}

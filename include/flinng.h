@@ -223,8 +223,9 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
  * flinng_query_noalloc -- flinng_query for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels and results, but every piece of scratch
- * (the batch's bucket codes, the SRP stage's norms, sign/flag words and
- * counters, the persistent grid's counter) comes from one 64 MiB device
+ * (the batch's bucket codes, the SRP stage's counters, operand planes and,
+ * for fp32 rows, norms and sign/flag words, the persistent grid's counter)
+ * comes from one 64 MiB device
  * array that the library holds per GPU until the process ends; nothing is
  * allocated or freed, and nothing is cleared with a memset call.
  *  q        device input only (q->on_device = 1), as in flinng_query.
@@ -232,11 +233,10 @@ int flinng_query_threshold(const flinng_index *idx, const flinng_input *q, uint3
  *           be NULL).
  * Returns once the work is enqueued on `stream`.  FLINNG_EINVAL when the
  * batch needs more scratch than the array holds (about nq*L*4 bytes plus,
- * for dense indexes, nq*(4 + 8*ceil(K*L/32)) bytes, for bf16 batches small
- * enough that the projection splits its k range into ns pieces
- * (ns <= ceil(dim/128)) ns*nq*K*L*4 bytes of partial projections, and,
- * unless bf16 rows with dim a multiple of 32 are used in place, the bf16
- * operand planes of nq*dim*2 bytes, three for fp32 rows): split the batch.
+ * for bf16 rows, one operand plane of nq*dim*2 bytes unless dim is a
+ * multiple of 32 and the rows are used in place, and for fp32 rows three
+ * planes of nq*dim*2 bytes and nq*(4 + 8*ceil(K*L/32)) bytes of norms and
+ * sign/flag words): split the batch.
  * Calls that overlap on one GPU share the array and race: serialize them
  * (one stream, or events).
  */

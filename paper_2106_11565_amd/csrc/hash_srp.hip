@@ -851,8 +851,9 @@ static bool srp_inplace(const Index &ix, const void *xdev) {
 // rows and its 48 hyperplanes: TM / (8 NW) + 6 KB): memory latency and the
 // wavefront's own load throughput.  Workgroups run in rounds of 256 times
 // the number a compute unit holds (8, 12 or 16 wavefronts for MR = 4, 2, 1),
-// and the whole grid's loads take at least their bytes at 10 TB/s; plus a
-// fixed 2 us.  KS needs nch >= 2 KS (the rounding bound).
+// and the whole grid's loads take at least their bytes at 6 TB/s (what
+// index-build chunks of 8,192 rows reached, with workgroups sharing compute
+// units); plus a fixed 2 us.  KS needs nch >= 2 KS (the rounding bound).
 struct SrpPlan {
     int mr, nw, ks;
     uint32_t gt;
@@ -869,7 +870,7 @@ static SrpPlan srp_plan(uint32_t K, uint32_t L, uint64_t n, uint32_t d) {
     static const int NWS[] = {1, 2, 3, 4, 6};
     static const int MRS[] = {1, 2, 4};
     static const int KSS[] = {1, 2, 4, 8};
-    const double A = 0.2e-6, B = 0.25e-6, BWG = 10e12, FIX = 2e-6;
+    const double A = 0.2e-6, B = 0.25e-6, BWG = 6e12, FIX = 2e-6;
     const uint32_t nch = (d + LCHK - 1) / LCHK;
     SrpPlan best{4, FMAXW, 1, 1, 0};
     double best_t = -1.0;
@@ -1014,8 +1015,9 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         // copy (zeros past d, which add nothing to any sum)
         const bool inplace = srp_inplace(ix, xdev);
         uint16_t *planes = sc.get<uint16_t>(inplace ? 0 : (size_t)n * dpad * 2);
-        unsigned long long *ctr = sc.get<unsigned long long>(16);
-        if (counters_host) {
+        // counters only when asked for (the kernel skips them otherwise)
+        unsigned long long *ctr = counters_host ? sc.get<unsigned long long>(16) : nullptr;
+        if (ctr) {
             hipLaunchKernelGGL(srp_zero_ctr_kernel, dim3(1), dim3(64), 0, s, ctr);
             FL_CHECK_LAUNCH();
         }
@@ -1028,7 +1030,7 @@ void srp_hash(const Index &ix, const flinng_input &in, uint32_t *codes_dev, hipS
         if (pl.wgs > 0x7FFFFFFFull) fail(FLINNG_EINVAL, "SRP batch too large for one launch");
         const SrpFusedArgs a{inplace ? static_cast<const uint16_t *>(xdev) : planes,
                              dpad, dpad, &ix, n, gamma, tau_abs, codes_dev,
-                             counters_host ? ctr : nullptr, proj_dev};
+                             ctr, proj_dev};
         switch (pl.mr) {
             case 1: srp_launch_ks<1>(pl, a, s); break;
             case 2: srp_launch_ks<2>(pl, a, s); break;

@@ -212,10 +212,20 @@ __global__ void unique_kernel(const uint64_t *__restrict__ keys, uint64_t n,
 template <typename CellT>
 __global__ void compact_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ flag,
                                const uint32_t *__restrict__ pos, uint64_t n, uint64_t cmask,
-                               CellT *__restrict__ out) {
+                               const uint64_t *__restrict__ tbase, CellT *__restrict__ out) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !flag[i]) return;
-    out[pos[i]] = (CellT)(keys[i] & cmask);
+    out[*tbase + pos[i]] = (CellT)(keys[i] & cmask);
+}
+
+// The running start of the tables' lists on the device: tb[t + 1] = tb[t] +
+// the unique entries of table t (pos and flag of its last key), so that the
+// tables' kernels queue without a host round trip per table.
+__global__ void list_total_kernel(const uint32_t *__restrict__ pos,
+                                  const uint32_t *__restrict__ flag, uint64_t n,
+                                  uint64_t *__restrict__ tb, uint32_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        tb[t + 1] = tb[t] + (n ? (uint64_t)pos[n - 1] + flag[n - 1] : 0ull);
 }
 
 // Bucket offsets without atomics, as a merge of two sorted sequences: the
@@ -226,16 +236,18 @@ __global__ void compact_kernel(const uint64_t *__restrict__ keys, const uint32_t
 // how many keys precede its first item, then it walks its items, consuming a
 // key or writing one offset per step.  The work per thread is bounded however
 // the keys crowd into few buckets (SRP codes of clustered data leave gaps of
-// millions of empty buckets); each offset is written exactly once.
-constexpr uint32_t OB_ITEMS = 128;
+// millions of empty buckets); each offset is written exactly once.  32 items
+// per thread: a few thousand workgroups for a table of millions of keys.
+constexpr uint32_t OB_ITEMS = 32;
 
 __global__ __launch_bounds__(256) void bucket_offsets_kernel(const uint64_t *__restrict__ keys,
                                                              const uint32_t *__restrict__ pos,
                                                              const uint32_t *__restrict__ flag,
                                                              uint64_t n, int cb, uint64_t nbk,
-                                                             uint32_t base,
+                                                             const uint64_t *__restrict__ tbase,
                                                              uint32_t *__restrict__ off) {
     const uint64_t total = nbk + 1 + n;
+    const uint32_t base = (uint32_t)*tbase;  // an overflow past 2^32 fails the build
     const uint64_t d = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * OB_ITEMS;
     if (d >= total) return;
     // the first key index i in [lo, hi) that does not go before bucket d-1-i
@@ -296,11 +308,13 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
     Lists out;
     out.tstart.assign(L + 1, 0);
     DevBuf keys(most * 8, s), tmp(most * 8, s), flag(most * 4, s), pos(most * 4, s);
+    DevBuf tbd((L + 1) * 8, s);  // the tables' list starts
+    uint64_t *tb = tbd.as<uint64_t>();
     void *big = nullptr;
     try {
         FL_HIP(hipMalloc(&out.offsets, (size_t)L * (nbk + 1) * 4));
         FL_HIP(hipMalloc(&big, std::max<uint64_t>(cap, 1) * csz));
-        uint64_t base = 0;
+        FL_HIP(hipMemsetAsync(tb, 0, 8, s));
         for (uint32_t t = 0; t < L; ++t) {
             const uint64_t nold = old_cells ? tstart_old[t + 1] - tstart_old[t] : 0;
             const uint64_t nk = nold + nr;
@@ -324,39 +338,39 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
                 FL_CHECK_LAUNCH();
             }
             radix_sort_u64(k, tmp.as<uint64_t>(), nullptr, nullptr, nk, end_bit, s);
-            uint64_t nt = 0;
             if (nk) {
                 const unsigned g1 = (unsigned)((nk + 255) / 256);
                 hipLaunchKernelGGL(unique_kernel, dim3(g1), dim3(256), 0, s, k, nk,
                                    flag.as<uint32_t>());
                 FL_CHECK_LAUNCH();
                 device_exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), nk, s);
-                uint32_t last[2];
-                FL_HIP(hipMemcpyAsync(&last[0], pos.as<uint32_t>() + nk - 1, 4, hipMemcpyDeviceToHost, s));
-                FL_HIP(hipMemcpyAsync(&last[1], flag.as<uint32_t>() + nk - 1, 4, hipMemcpyDeviceToHost, s));
-                FL_HIP(hipStreamSynchronize(s));
-                nt = (uint64_t)last[0] + last[1];
-                if (base + nt > 0xFFFFFFFFull) fail(FLINNG_EINVAL, "reverse index exceeds 2^32 entries");
                 const uint64_t cmask = (1ull << cb) - 1;
+                // the list starts at tb[t]; big holds every key, so the
+                // writes stay inside it whatever the total comes to
                 if (csz == 2)
                     hipLaunchKernelGGL(compact_kernel<uint16_t>, dim3(g1), dim3(256), 0, s, k,
-                                       flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask,
-                                       static_cast<uint16_t *>(big) + base);
+                                       flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask, tb + t,
+                                       static_cast<uint16_t *>(big));
                 else
                     hipLaunchKernelGGL(compact_kernel<uint32_t>, dim3(g1), dim3(256), 0, s, k,
-                                       flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask,
-                                       static_cast<uint32_t *>(big) + base);
+                                       flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask, tb + t,
+                                       static_cast<uint32_t *>(big));
                 FL_CHECK_LAUNCH();
             }
+            hipLaunchKernelGGL(list_total_kernel, dim3(1), dim3(64), 0, s, pos.as<uint32_t>(),
+                               flag.as<uint32_t>(), nk, tb, t);
+            FL_CHECK_LAUNCH();
             const uint64_t nthr = (nbk + 1 + nk + OB_ITEMS - 1) / OB_ITEMS;
             hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)((nthr + 255) / 256)),
                                dim3(256), 0, s, k, pos.as<uint32_t>(), flag.as<uint32_t>(), nk, cb,
-                               nbk, (uint32_t)base, out.offsets + (uint64_t)t * (nbk + 1));
+                               nbk, tb + t, out.offsets + (uint64_t)t * (nbk + 1));
             FL_CHECK_LAUNCH();
-            out.tstart[t] = base;
-            base += nt;
         }
-        out.tstart[L] = base;
+        // one read-back of the tables' list starts
+        FL_HIP(hipMemcpyAsync(out.tstart.data(), tb, (L + 1) * 8, hipMemcpyDeviceToHost, s));
+        FL_HIP(hipStreamSynchronize(s));
+        const uint64_t base = out.tstart[L];
+        if (base > 0xFFFFFFFFull) fail(FLINNG_EINVAL, "reverse index exceeds 2^32 entries");
         // shrink the list buffer to its size plus a zeroed tail, so that the
         // query kernel's 16-byte chunk reads past a list's end stay inside it
         const size_t used = (size_t)base * csz;

@@ -173,3 +173,28 @@ def test_url_full_sampled(env):
     q_d = (_dev(torch, queries[0]), _dev(torch, queries[1]))
     p_i, _ = _query_dev(torch, fl, gi, q_d, len(queries[1]) - 1, persistent=True)
     assert np.array_equal(p_i, got_i)
+
+
+def test_relu_tuned_hash_every_batch_plan(env):
+    """The SRP stage at the benchmark's tuned (K, L) = (24, 12), d = 4096,
+    for the batch sizes whose kernel plans the benchmark runs: a full
+    10,000-query batch, an 8,192-row index-build chunk, served batches of
+    2,900 and 2,048, small ones of 512, 128 and 1.  Each batch is hashed
+    on the device in one call; 40 sampled rows of each must equal the
+    oracle's codes (FP64 / exact signs)."""
+    torch, fl = env
+    from workloads import synth
+    X, Q, _ = synth.dense_relu(N=20000, d=4096, n_centres=200, nq=10000)
+    assert Q.shape[0] == 10000
+    K, L, seed = 24, 12, configs.INDEX_SEED
+    gi = fl.Index(X[:4000], fl.SRP_BF16, K, L, 4, 100, seed)
+    w = oracle.hyperplanes(seed, K * L, 4096)
+    rng = np.random.default_rng(3)
+    q_d = _dev(torch, Q)
+    for n in (10000, 8192, 2900, 2048, 512, 128, 1):
+        codes = gi.debug_hash(q_d[:n].contiguous())
+        codes = codes.cpu().numpy() if hasattr(codes, "cpu") else np.asarray(codes)
+        rows = np.sort(rng.choice(n, min(n, 40), replace=False))
+        want = oracle.srp_codes(oracle.bf16_to_f64(Q[rows]), seed, K, L, w=w)
+        log("tuned hash", n, "rows checked", len(rows))
+        assert np.array_equal(codes.reshape(n, L)[rows].astype(np.uint32), want.astype(np.uint32)), n

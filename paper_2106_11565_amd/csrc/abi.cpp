@@ -183,8 +183,13 @@ static void build_impl(const flinng_params *p, const flinng_input *data, hipStre
         }
         // hash all points (in chunks to bound scratch memory)
         DevBuf codes(N * p->L * 4, s);
-        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix->dpad * 16))
-                                     : (1ull << 20);
+        // dense chunks bound the SRP scratch (a device copy of host rows,
+        // operand planes): 512 MB of bf16 rows (the fused kernel takes them
+        // in place, and larger batches fill more rounds of workgroups), or
+        // 512 MB of fp32 rows with their three bf16 planes
+        const uint64_t per_row =
+            (uint64_t)ix->dpad * (p->family == FLINNG_SRP_BF16 ? 2 : 16);
+        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / per_row) : (1ull << 20);
         for (uint64_t b0 = 0; b0 < N; b0 += chunk) {
             const uint64_t n = std::min(chunk, N - b0);
             flinng_input part = slice(*data, *ix, b0, n);
@@ -241,7 +246,9 @@ int flinng_index_insert(flinng_index *idx, const flinng_input *data, void *strea
         require(ix.N + n <= 0xFFFFFFFEull, "at most 2^32-2 points");
         const bool dense = is_dense(ix.p.family);
         DevBuf codes(n * ix.p.L * 4, s);
-        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / ((uint64_t)ix.dpad * 16))
+        const uint64_t per_row =
+            (uint64_t)ix.dpad * (ix.p.family == FLINNG_SRP_BF16 ? 2 : 16);  // as in the build
+        const uint64_t chunk = dense ? std::max<uint64_t>(1, (1ull << 29) / per_row)
                                      : (1ull << 20);
         uint64_t rechecked = 0, exact = 0;
         for (uint64_t b0 = 0; b0 < n; b0 += chunk) {

@@ -844,16 +844,19 @@ static bool srp_inplace(const Index &ix, const void *xdev) {
 
 // How srp_fused_kernel covers n rows: MR (tile rows / 16), NW (column
 // wavefronts), KS (k groups) and gt (tables per group), from a model fitted
-// to kernel times on MI355X (ReLU embeddings, d = 4096, K*L = 288, batches of
-// 128 to 10,000 rows; every plan within 15% of the best one measured).  A
-// workgroup takes steps = 2 ceil(nch / KS) 64-wide steps, each about
-// 0.2 us + 0.25 us per KB that one wavefront loads in it (its share of the
-// rows and its 48 hyperplanes: TM / (8 NW) + 6 KB): memory latency and the
-// wavefront's own load throughput.  Workgroups run in rounds of 256 times
-// the number a compute unit holds (8, 12 or 16 wavefronts for MR = 4, 2, 1),
-// and the whole grid's loads take at least their bytes at 6 TB/s (what
-// index-build chunks of 8,192 rows reached, with workgroups sharing compute
-// units); plus a fixed 2 us.  KS needs nch >= 2 KS (the rounding bound).
+// to kernel traces on MI355X (ReLU embeddings, d = 4096, K*L = 288 and 1024,
+// batches of 128 to 65,536 rows: at every size measured its plan is within
+// 16% of the best one, and the best one from 8,192 rows up).  A workgroup
+// takes steps = 2 ceil(nch / KS) 64-wide steps, each about 0.2 us + 0.1 us
+// per KB that one wavefront loads in it (its share of the rows and its 48
+// hyperplanes: TM / (8 NW) + 6 KB), longer by 4% per further wavefront of
+// the workgroup (they step together) in proportion to how full the chip is.
+// Workgroups run in rounds of 256 times the number a compute unit holds (8,
+// 12 or 16 wavefronts for MR = 4, 2, 1).  The grid's loads take at least
+// their bytes at 10 TB/s, counting each row once per row tile (the table
+// groups of a tile run on one XCD and share its L2) and the hyperplanes once
+// per workgroup; plus a fixed 4 us.  Within 2% the plan with more workgroups
+// wins.  KS needs nch >= 2 KS (the rounding bound).
 struct SrpPlan {
     int mr, nw, ks;
     uint32_t gt;
@@ -870,7 +873,7 @@ static SrpPlan srp_plan(uint32_t K, uint32_t L, uint64_t n, uint32_t d) {
     static const int NWS[] = {1, 2, 3, 4, 6};
     static const int MRS[] = {1, 2, 4};
     static const int KSS[] = {1, 2, 4, 8};
-    const double A = 0.2e-6, B = 0.25e-6, BWG = 6e12, FIX = 2e-6;
+    const double A = 0.2e-6, B = 0.1e-6, C = 0.04, BWG = 10e12, FIX = 4e-6;
     const uint32_t nch = (d + LCHK - 1) / LCHK;
     SrpPlan best{4, FMAXW, 1, 1, 0};
     double best_t = -1.0;
@@ -894,9 +897,13 @@ static SrpPlan srp_plan(uint32_t K, uint32_t L, uint64_t n, uint32_t d) {
                 const double kbw = (double)tm / (8.0 * nw) + 6.0;
                 const uint64_t occ = (uint64_t)std::max(1, wcu / (nw * ks));
                 const double rounds = (double)((wgs + 256 * occ - 1) / (256 * occ));
-                const double bytes = (double)wgs * ks * steps * (double)(tm + FW * nw) * 128.0;
-                const double t = std::max(rounds * steps * (A + B * kbw), bytes / BWG) + FIX;
-                if (best_t < 0.0 || t < best_t || (t == best_t && wgs < best.wgs)) {
+                const double bytes = 2.0 * d * (double)(nrt * tm + wgs * (uint64_t)(FW * nw));
+                const double load = std::min(1.0, (double)wgs / (256.0 * (double)occ));
+                const double step = (A + B * kbw) * (1.0 + C * (nw * ks - 1) * load);
+                const double t = std::max(rounds * steps * step, bytes / BWG) + FIX;
+                // within 2% of the best so far, the plan with more workgroups
+                // (the bandwidth bound ties plans the traces tell apart)
+                if (best_t < 0.0 || t < 0.98 * best_t || (t <= 1.02 * best_t && wgs > best.wgs)) {
                     best = SrpPlan{mr, nw, ks, gt, wgs};
                     best_t = t;
                 }

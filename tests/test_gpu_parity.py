@@ -98,6 +98,23 @@ def _cancelling_rows(w, rng, nrand, boost=2.0**6, tiny=2.0**-20):
     return np.stack(rows)
 
 
+@pytest.mark.parametrize("n,d,K,L", [(1, 1024, 13, 40), (17, 2080, 24, 12), (300, 2080, 7, 41),
+                                     (1000, 1024, 16, 19), (2500, 4064, 5, 60), (129, 4064, 24, 13)])
+def test_srp_bf16_k_groups_and_table_groups(fl, n, d, K, L):
+    """bf16 rows through the fused SRP kernel's k-split and table-group
+    paths: d = 1024 (8 chunks of 128), 2080 (16 chunks and a final half
+    step of 32) and 4064 (a final chunk of 96), K*L above 288 so a row tile
+    spans several groups of whole tables (the last one ragged), and ragged
+    row counts; codes equal the oracle's."""
+    log("srp bf16 k groups", n, d, K, L)
+    rng = np.random.default_rng(n * 7 + d + K * L)
+    x = synth.f32_to_bf16(rng.standard_normal((n, d)).astype(np.float32))
+    gi = fl.Index(x, 1, K, L, 2, max(1, n // 4), seed=4321)
+    w = oracle.hyperplanes(4321, K * L, d)
+    want = oracle.srp_codes(oracle.bf16_to_f64(x), 4321, K, L, w=w)
+    assert np.array_equal(gi.debug_hash(x), want)
+
+
 @pytest.mark.parametrize("n,d,K,L", [(2048, 4096, 24, 12), (3000, 256, 16, 7), (4000, 512, 24, 12),
                                      (700, 96, 24, 5), (600, 100, 24, 5), (1500, 64, 3, 33)])
 def test_srp_bf16_rechecks_only_near_zero(fl, n, d, K, L):

@@ -239,25 +239,49 @@ __global__ void list_total_kernel(const uint32_t *__restrict__ pos,
 // millions of empty buckets); each offset is written exactly once.  32 items
 // per thread: a few thousand workgroups for a table of millions of keys.
 constexpr uint32_t OB_ITEMS = 32;
+constexpr uint64_t OB_BLOCK = 256ull * OB_ITEMS;  // merged items per workgroup
+
+// Where the merge path crosses diagonal d: the first key index i in [lo, hi)
+// that does not go before bucket d-1-i.
+__device__ inline uint64_t ob_cross(const uint64_t *__restrict__ keys, int cb, uint64_t d,
+                                    uint64_t lo, uint64_t hi) {
+    while (lo < hi) {
+        const uint64_t m = (lo + hi) / 2;
+        if ((keys[m] >> cb) + 1 + m < d) lo = m + 1;  // bucket(keys[m]) < d-1-m
+        else hi = m;
+    }
+    return lo;
+}
+
+// The crossings of the workgroups' first diagonals (one thread each): the
+// crossing only grows along the path, so a thread of bucket_offsets_kernel
+// then searches its workgroup's stretch of at most OB_BLOCK keys, mostly in
+// cache, instead of the whole table.
+__global__ void bucket_blocks_kernel(const uint64_t *__restrict__ keys, uint64_t n, int cb,
+                                     uint64_t nbk, uint64_t nblk, uint64_t *__restrict__ blo) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nblk) return;
+    const uint64_t total = nbk + 1 + n;
+    const uint64_t d = b * OB_BLOCK < total ? b * OB_BLOCK : total;
+    blo[b] = ob_cross(keys, cb, d, d > nbk + 1 ? d - (nbk + 1) : 0, d < n ? d : n);
+}
 
 __global__ __launch_bounds__(256) void bucket_offsets_kernel(const uint64_t *__restrict__ keys,
                                                              const uint32_t *__restrict__ pos,
                                                              const uint32_t *__restrict__ flag,
                                                              uint64_t n, int cb, uint64_t nbk,
+                                                             const uint64_t *__restrict__ blo,
                                                              const uint64_t *__restrict__ tbase,
                                                              uint32_t *__restrict__ off) {
     const uint64_t total = nbk + 1 + n;
     const uint32_t base = (uint32_t)*tbase;  // an overflow past 2^32 fails the build
     const uint64_t d = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * OB_ITEMS;
     if (d >= total) return;
-    // the first key index i in [lo, hi) that does not go before bucket d-1-i
+    // the crossing of d lies between those of the workgroup's diagonals
     uint64_t lo = d > nbk + 1 ? d - (nbk + 1) : 0, hi = d < n ? d : n;
-    while (lo < hi) {
-        const uint64_t m = (lo + hi) / 2;
-        if ((keys[m] >> cb) + 1 + m < d) lo = m + 1;  // bucket(keys[m]) < d-1-m
-        else hi = m;
-    }
-    uint64_t i = lo, b = d - lo;
+    lo = lo > blo[blockIdx.x] ? lo : blo[blockIdx.x];
+    hi = hi < blo[blockIdx.x + 1] ? hi : blo[blockIdx.x + 1];
+    uint64_t i = ob_cross(keys, cb, d, lo, hi), b = d - i;
     const uint32_t last = n ? pos[n - 1] + flag[n - 1] : 0u;
     const uint64_t end = d + OB_ITEMS < total ? d + OB_ITEMS : total;
     for (uint64_t e = d; e < end; ++e) {
@@ -310,6 +334,8 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
     DevBuf keys(most * 8, s), tmp(most * 8, s), flag(most * 4, s), pos(most * 4, s);
     DevBuf tbd((L + 1) * 8, s);  // the tables' list starts
     uint64_t *tb = tbd.as<uint64_t>();
+    const uint64_t nblk_most = (nbk + 1 + most + OB_BLOCK - 1) / OB_BLOCK;
+    DevBuf blod((nblk_most + 1) * 8, s);  // merge-path crossings per workgroup
     void *big = nullptr;
     try {
         FL_HIP(hipMalloc(&out.offsets, (size_t)L * (nbk + 1) * 4));
@@ -360,10 +386,13 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
             hipLaunchKernelGGL(list_total_kernel, dim3(1), dim3(64), 0, s, pos.as<uint32_t>(),
                                flag.as<uint32_t>(), nk, tb, t);
             FL_CHECK_LAUNCH();
-            const uint64_t nthr = (nbk + 1 + nk + OB_ITEMS - 1) / OB_ITEMS;
-            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)((nthr + 255) / 256)),
-                               dim3(256), 0, s, k, pos.as<uint32_t>(), flag.as<uint32_t>(), nk, cb,
-                               nbk, tb + t, out.offsets + (uint64_t)t * (nbk + 1));
+            const uint64_t nblk = (nbk + 1 + nk + OB_BLOCK - 1) / OB_BLOCK;
+            hipLaunchKernelGGL(bucket_blocks_kernel, dim3((unsigned)((nblk + 1 + 255) / 256)),
+                               dim3(256), 0, s, k, nk, cb, nbk, nblk, blod.as<uint64_t>());
+            FL_CHECK_LAUNCH();
+            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, k,
+                               pos.as<uint32_t>(), flag.as<uint32_t>(), nk, cb, nbk,
+                               blod.as<uint64_t>(), tb + t, out.offsets + (uint64_t)t * (nbk + 1));
             FL_CHECK_LAUNCH();
         }
         // one read-back of the tables' list starts

@@ -363,10 +363,12 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
                                    0, s, codes, grp_rows, n, L, t, R, ix.Rp, Bp, cb, k + nold);
                 FL_CHECK_LAUNCH();
             }
-            radix_sort_u64(k, tmp.as<uint64_t>(), nullptr, nullptr, nk, end_bit, s);
+            // the sorted keys stay in whichever buffer the last pass wrote
+            uint64_t *ks = k;
+            radix_sort_u64(k, tmp.as<uint64_t>(), nullptr, nullptr, nk, end_bit, s, &ks);
             if (nk) {
                 const unsigned g1 = (unsigned)((nk + 255) / 256);
-                hipLaunchKernelGGL(unique_kernel, dim3(g1), dim3(256), 0, s, k, nk,
+                hipLaunchKernelGGL(unique_kernel, dim3(g1), dim3(256), 0, s, ks, nk,
                                    flag.as<uint32_t>());
                 FL_CHECK_LAUNCH();
                 device_exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), nk, s);
@@ -374,11 +376,11 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
                 // the list starts at tb[t]; big holds every key, so the
                 // writes stay inside it whatever the total comes to
                 if (csz == 2)
-                    hipLaunchKernelGGL(compact_kernel<uint16_t>, dim3(g1), dim3(256), 0, s, k,
+                    hipLaunchKernelGGL(compact_kernel<uint16_t>, dim3(g1), dim3(256), 0, s, ks,
                                        flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask, tb + t,
                                        static_cast<uint16_t *>(big));
                 else
-                    hipLaunchKernelGGL(compact_kernel<uint32_t>, dim3(g1), dim3(256), 0, s, k,
+                    hipLaunchKernelGGL(compact_kernel<uint32_t>, dim3(g1), dim3(256), 0, s, ks,
                                        flag.as<uint32_t>(), pos.as<uint32_t>(), nk, cmask, tb + t,
                                        static_cast<uint32_t *>(big));
                 FL_CHECK_LAUNCH();
@@ -388,9 +390,9 @@ Lists assemble_lists(const Index &ix, const uint32_t *old_off, const void *old_c
             FL_CHECK_LAUNCH();
             const uint64_t nblk = (nbk + 1 + nk + OB_BLOCK - 1) / OB_BLOCK;
             hipLaunchKernelGGL(bucket_blocks_kernel, dim3((unsigned)((nblk + 1 + 255) / 256)),
-                               dim3(256), 0, s, k, nk, cb, nbk, nblk, blod.as<uint64_t>());
+                               dim3(256), 0, s, ks, nk, cb, nbk, nblk, blod.as<uint64_t>());
             FL_CHECK_LAUNCH();
-            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, k,
+            hipLaunchKernelGGL(bucket_offsets_kernel, dim3((unsigned)nblk), dim3(256), 0, s, ks,
                                pos.as<uint32_t>(), flag.as<uint32_t>(), nk, cb, nbk,
                                blod.as<uint64_t>(), tb + t, out.offsets + (uint64_t)t * (nbk + 1));
             FL_CHECK_LAUNCH();

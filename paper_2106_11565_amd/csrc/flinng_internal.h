@@ -249,8 +249,11 @@ void device_exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n,
                                hipStream_t s);
 // Stable LSD radix sort of 64-bit keys (bits [0, end_bit)) with optional
 // uint32 values; result in keys/vals (tmp buffers of the same size needed).
+// Keys alone (vals == nullptr) with `sorted` given: the result stays in
+// whichever of keys / keys_tmp the last pass wrote, returned in *sorted.
 void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals,
-                    uint32_t *vals_tmp, uint64_t n, int end_bit, hipStream_t s);
+                    uint32_t *vals_tmp, uint64_t n, int end_bit, hipStream_t s,
+                    uint64_t **sorted = nullptr);
 
 // Build pieces (build.hip).
 void build_groups(Index &ix, hipStream_t s);

@@ -166,7 +166,9 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
 }
 
 void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals, uint32_t *vals_tmp,
-                    uint64_t n, int end_bit, hipStream_t s) {
+                    uint64_t n, int end_bit, hipStream_t s, uint64_t **sorted) {
+    if (sorted && vals) fail(FLINNG_EDEVICE, "internal: radix sort result left in place with values");
+    if (sorted) *sorted = keys;
     if (n <= 1 || end_bit <= 0) return;
     const uint64_t nb = (n + RS_TILE - 1) / RS_TILE;
     DevBuf hist(256 * nb * 4, s), goff(256 * nb * 4, s);
@@ -183,6 +185,10 @@ void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals, uint32_t
         FL_CHECK_LAUNCH();
         std::swap(kin, kout);
         std::swap(vin, vout);
+    }
+    if (sorted) {
+        *sorted = kin;  // no copy back
+        return;
     }
     if (passes % 2 == 1) {
         FL_HIP(hipMemcpyAsync(keys, kin, n * 8, hipMemcpyDeviceToDevice, s));

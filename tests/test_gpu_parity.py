@@ -271,6 +271,29 @@ def test_degenerate_grids(fl, R, B, L, k):
     _check_all(fl, 0, X, Q, 6, L, R, B, 11, 0, ks=(k,))
 
 
+def test_skewed_codes_and_mostly_empty_buckets(fl):
+    """Nine points in ten are the same set, so before deduplication one
+    bucket of every table holds most of the table's keys, and the tables
+    have 2^20 buckets, nearly all empty: the build's merge of the bucket
+    numbers with the sorted keys then has workgroups that see only keys of
+    one bucket and workgroups that see only empty buckets.  The offsets,
+    lists and query results must equal the oracle's."""
+    rng = np.random.default_rng(41)
+    n = 12000
+    items, offs = random_sets(rng, n, 40, np.uint32)
+    common = rng.integers(0, 2**32, 40, dtype=np.int64).astype(np.uint32)
+    same = rng.random(n) < 0.9
+    parts = [common if same[i] else items[offs[i]:offs[i + 1]] for i in range(n)]
+    o = np.zeros(n + 1, dtype=np.uint64)
+    o[1:] = np.cumsum([len(p) for p in parts])
+    it = np.concatenate(parts).astype(np.uint32)
+    sel = np.concatenate([np.nonzero(same)[0][:5], np.nonzero(~same)[0][:45]])
+    q = subset_sets(it, o, sel)
+    log("skewed", int(same.sum()), "of", n, "points share one set")
+    gi, oi = _check_all(fl, 2, (it, o), q, 2, 4, 4, 50, 19, 20, ks=(10, 200))
+    assert gi.info.list_entries == oi.cells.size
+
+
 def test_identical_queries_returned_with_full_score(fl):
     X, _, _ = synth.dense_gmm(N=5000, d=64, n_centres=200, sigma=0.05, nq=1)
     gi = fl.Index(X, 0, 12, 16, 3, 250, seed=3)

@@ -237,9 +237,13 @@ __global__ void list_total_kernel(const uint32_t *__restrict__ pos,
 // key or writing one offset per step.  The work per thread is bounded however
 // the keys crowd into few buckets (SRP codes of clustered data leave gaps of
 // millions of empty buckets); each offset is written exactly once.  32 items
-// per thread: a few thousand workgroups for a table of millions of keys.
+// per thread: a few thousand workgroups for a table of millions of keys.  A
+// workgroup's offsets form one contiguous run of at most OB_BLOCK buckets, so
+// they are gathered in LDS and written out with whole-line stores.
 constexpr uint32_t OB_ITEMS = 32;
 constexpr uint64_t OB_BLOCK = 256ull * OB_ITEMS;  // merged items per workgroup
+constexpr uint32_t OB_LDS = OB_BLOCK + OB_BLOCK / 32;  // one pad word per 32
+__device__ inline uint32_t ob_pad(uint64_t j) { return (uint32_t)(j + (j >> 5)); }
 
 // Where the merge path crosses diagonal d: the first key index i in [lo, hi)
 // that does not go before bucket d-1-i.
@@ -273,25 +277,44 @@ __global__ __launch_bounds__(256) void bucket_offsets_kernel(const uint64_t *__r
                                                              const uint64_t *__restrict__ blo,
                                                              const uint64_t *__restrict__ tbase,
                                                              uint32_t *__restrict__ off) {
+    __shared__ uint32_t run[OB_LDS];
     const uint64_t total = nbk + 1 + n;
     const uint32_t base = (uint32_t)*tbase;  // an overflow past 2^32 fails the build
-    const uint64_t d = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * OB_ITEMS;
-    if (d >= total) return;
-    // the crossing of d lies between those of the workgroup's diagonals
-    uint64_t lo = d > nbk + 1 ? d - (nbk + 1) : 0, hi = d < n ? d : n;
-    lo = lo > blo[blockIdx.x] ? lo : blo[blockIdx.x];
-    hi = hi < blo[blockIdx.x + 1] ? hi : blo[blockIdx.x + 1];
-    uint64_t i = ob_cross(keys, cb, d, lo, hi), b = d - i;
-    const uint32_t last = n ? pos[n - 1] + flag[n - 1] : 0u;
-    const uint64_t end = d + OB_ITEMS < total ? d + OB_ITEMS : total;
-    for (uint64_t e = d; e < end; ++e) {
-        if (i < n && (b > nbk || (keys[i] >> cb) < b)) {
-            ++i;
-        } else {
-            off[b] = base + (i < n ? pos[i] : last);
-            ++b;
+    // the workgroup's diagonals [d0, d1) emit the buckets [b0, b1)
+    const uint64_t d0 = (uint64_t)blockIdx.x * OB_BLOCK;
+    const uint64_t d1 = d0 + OB_BLOCK < total ? d0 + OB_BLOCK : total;
+    const uint64_t c0 = blo[blockIdx.x], c1 = blo[blockIdx.x + 1];
+    const uint64_t b0 = d0 - c0, b1 = d1 - c1;
+    const uint64_t d = d0 + (uint64_t)threadIdx.x * OB_ITEMS;
+    if (d < total) {
+        // the crossing of d lies between those of the workgroup's diagonals
+        uint64_t lo = d > nbk + 1 ? d - (nbk + 1) : 0, hi = d < n ? d : n;
+        lo = lo > c0 ? lo : c0;
+        hi = hi < c1 ? hi : c1;
+        uint64_t i = ob_cross(keys, cb, d, lo, hi), b = d - i;
+        const uint32_t last = n ? pos[n - 1] + flag[n - 1] : 0u;
+        const uint64_t end = d + OB_ITEMS < total ? d + OB_ITEMS : total;
+        uint64_t kb = i < n ? keys[i] >> cb : 0;  // bucket of key i
+        uint32_t pv = 0;                          // pos of key i, once read
+        bool have = false;
+        for (uint64_t e = d; e < end; ++e) {
+            if (i < n && (b > nbk || kb < b)) {
+                ++i;
+                if (i < n) kb = keys[i] >> cb;
+                have = false;
+            } else {
+                if (!have) {
+                    pv = i < n ? pos[i] : last;
+                    have = true;
+                }
+                run[ob_pad(b - b0)] = base + pv;
+                ++b;
+            }
         }
     }
+    __syncthreads();
+    uint32_t *o = off + b0;
+    for (uint64_t j = threadIdx.x; j < b1 - b0; j += blockDim.x) o[j] = run[ob_pad(j)];
 }
 
 namespace {

@@ -115,16 +115,27 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint64_t *__r
 
 // Stable scatter: rounds of 256 keys in input order; within a round each
 // key's rank among equal digits comes from the wavefront's digit-match mask
-// (8 ballots) and per-wave digit counts combined in LDS.
+// (8 ballots) and per-wave digit counts combined in LDS.  The ranks place the
+// tile's keys in LDS ordered by digit (the tile's digit counts from hist give
+// each digit's start there); the tile is then written out in that order, so
+// consecutive threads store consecutive addresses of a digit's run.
+template <bool VALS>
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t n, int shift,
-    uint64_t nb, const uint32_t *__restrict__ goff, uint64_t *__restrict__ okeys,
-    uint32_t *__restrict__ ovals) {
+    uint64_t nb, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ goff,
+    uint64_t *__restrict__ okeys, uint32_t *__restrict__ ovals) {
     __shared__ uint32_t wcnt[RS_THREADS / 64][256];
     __shared__ uint32_t woff[RS_THREADS / 64][256];
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t run[256];    // next local position per digit
+    __shared__ uint32_t gdel[256];   // global start minus local start, per digit
+    __shared__ uint32_t sl[RS_THREADS / 64];
+    __shared__ uint64_t tk[RS_TILE];
+    __shared__ uint32_t tv[VALS ? RS_TILE : 1];
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-    run[t] = goff[(uint64_t)t * nb + blockIdx.x];
+    uint32_t tot;
+    const uint32_t ls = block_exclusive_scan(hist[(uint64_t)t * nb + blockIdx.x], sl, &tot);
+    run[t] = ls;
+    gdel[t] = goff[(uint64_t)t * nb + blockIdx.x] - ls;
 #pragma unroll
     for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][t] = 0;
     __syncthreads();
@@ -134,7 +145,7 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
         const uint64_t p = base + (uint64_t)i * RS_THREADS + t;
         const bool valid = p < n;
         uint64_t key = valid ? keys[p] : 0ull;
-        uint32_t val = (valid && vals) ? vals[p] : 0u;
+        uint32_t val = (VALS && valid) ? vals[p] : 0u;
         const uint32_t dgt = (uint32_t)((key >> shift) & 255u);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -158,10 +169,18 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
         }
         __syncthreads();
         if (valid) {
-            const uint32_t pos = woff[wave][dgt] + rank;
-            okeys[pos] = key;
-            if (vals) ovals[pos] = val;
+            const uint32_t lp = woff[wave][dgt] + rank;  // < the tile's key count
+            tk[lp] = key;
+            if (VALS) tv[lp] = val;
         }
+    }
+    __syncthreads();
+    const uint64_t m = n - base < (uint64_t)RS_TILE ? n - base : (uint64_t)RS_TILE;
+    for (uint32_t j = t; j < m; j += RS_THREADS) {
+        const uint64_t key = tk[j];
+        const uint32_t gp = gdel[(uint32_t)((key >> shift) & 255u)] + j;
+        okeys[gp] = key;
+        if (VALS) ovals[gp] = tv[j];
     }
 }
 
@@ -180,8 +199,14 @@ void radix_sort_u64(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals, uint32_t
                            shift, nb, hist.as<uint32_t>());
         FL_CHECK_LAUNCH();
         device_exclusive_scan_u32(hist.as<uint32_t>(), goff.as<uint32_t>(), 256 * nb, s);
-        hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, kin,
-                           vin, n, shift, nb, goff.as<uint32_t>(), kout, vout);
+        if (vals)
+            hipLaunchKernelGGL(rs_scatter_kernel<true>, dim3((unsigned)nb), dim3(RS_THREADS), 0, s,
+                               kin, vin, n, shift, nb, hist.as<uint32_t>(), goff.as<uint32_t>(),
+                               kout, vout);
+        else
+            hipLaunchKernelGGL(rs_scatter_kernel<false>, dim3((unsigned)nb), dim3(RS_THREADS), 0,
+                               s, kin, (const uint32_t *)nullptr, n, shift, nb,
+                               hist.as<uint32_t>(), goff.as<uint32_t>(), kout, (uint32_t *)nullptr);
         FL_CHECK_LAUNCH();
         std::swap(kin, kout);
         std::swap(vin, vout);
